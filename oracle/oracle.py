@@ -1,0 +1,226 @@
+"""ctypes binding of the serial FP64 CPU oracle (``wombat_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the CPU-baseline leg
+of the benchmark use this module to check the GPU library; the product path
+never imports it, and it imports nothing from the product package.
+
+Method: Donnert et al., arXiv:1808.10633, Sec. 2.1 (characteristic WENO5
+finite differences, eqs. 1-7, RK4, constrained transport) and Sec. 2.2
+(3 ghost zones, x/y/z sweeps).  See the C source for the readings adopted
+where the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wombat_oracle.c")
+_LIB = os.path.join(_HERE, "libwombat_oracle.so")
+
+# No fast-math and no FMA contraction: every operation rounds as written.
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/libwombat_oracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("eps", C.c_double),
+                ("bc", C.c_int * 6)]
+
+
+@dataclass
+class Grid:
+    """Box description; an axis with n == 1 is inactive (no ghosts, no sweep)."""
+    nx: int
+    ny: int = 1
+    nz: int = 1
+    dx: float = 1.0
+    dy: float = 1.0
+    dz: float = 1.0
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.4
+    eps: float = 1e-6
+    bc: tuple = field(default_factory=lambda: (0, 0, 0, 0, 0, 0))   # 0 periodic, 1 outflow
+
+    def c(self) -> _Grid:
+        g = _Grid(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
+                  self.gamma, self.cfl, self.eps)
+        for i in range(6):
+            g.bc[i] = int(self.bc[i])
+        return g
+
+    @property
+    def ghosts(self):
+        return tuple(3 if n > 1 else 0 for n in (self.nx, self.ny, self.nz))
+
+    @property
+    def shape(self):
+        """(8, NZ, NY, NX) padded state shape."""
+        gx, gy, gz = self.ghosts
+        return (8, self.nz + 2 * gz, self.ny + 2 * gy, self.nx + 2 * gx)
+
+    def interior(self, u):
+        gx, gy, gz = self.ghosts
+        return u[:, gz:gz + self.nz, gy:gy + self.ny, gx:gx + self.nx]
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        d = C.c_double
+        L.orc_weno_weights.argtypes = [d, d, d, d, d, _dp, _dp]
+        L.orc_weno_phi.argtypes = [d, d, d, d, d]
+        L.orc_weno_phi.restype = d
+        L.orc_weno_field_flux.argtypes = [_dp, _dp, d, d]
+        L.orc_weno_field_flux.restype = d
+        L.orc_prim_to_cons.argtypes = [_dp, d, _dp]
+        L.orc_cons_to_prim.argtypes = [_dp, d, _dp]
+        L.orc_flux.argtypes = [_dp, C.c_int, d, _dp]
+        L.orc_wave_speeds.argtypes = [_dp, C.c_int, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
+        L.orc_eigensystem.argtypes = [_dp, d, _dp, _dp, _dp]
+        L.orc_interface_flux.argtypes = [_dp, d, d, _dp]
+        g = C.POINTER(_Grid)
+        L.orc_state_size.argtypes = [g]
+        L.orc_state_size.restype = C.c_long
+        L.orc_fill_ghosts.argtypes = [g, _dp]
+        L.orc_rhs.argtypes = [g, _dp, _dp]
+        L.orc_rhs.restype = C.c_int
+        L.orc_cfl_dt.argtypes = [g, _dp]
+        L.orc_cfl_dt.restype = d
+        L.orc_rk4_step.argtypes = [g, _dp, d]
+        L.orc_rk4_step.restype = C.c_int
+        L.orc_sums.argtypes = [g, _dp, _dp]
+        L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---- scalar WENO (eqs. 1-7) ----
+def weno_weights(a, b, c, d, eps=1e-6):
+    w = np.zeros(3)
+    s = np.zeros(3)
+    lib().orc_weno_weights(a, b, c, d, eps, w, s)
+    return w, s
+
+
+def weno_phi(a, b, c, d, eps=1e-6):
+    return lib().orc_weno_phi(a, b, c, d, eps)
+
+
+def weno_field_flux(f, u, alpha, eps=1e-6):
+    return lib().orc_weno_field_flux(_f64(f), _f64(u), float(alpha), eps)
+
+
+# ---- point functions ----
+def prim_to_cons(W, gamma=5.0 / 3.0):
+    U = np.zeros(8)
+    lib().orc_prim_to_cons(_f64(W), gamma, U)
+    return U
+
+
+def cons_to_prim(U, gamma=5.0 / 3.0):
+    W = np.zeros(8)
+    lib().orc_cons_to_prim(_f64(U), gamma, W)
+    return W
+
+
+def flux(U, direction, gamma=5.0 / 3.0):
+    F = np.zeros(8)
+    lib().orc_flux(_f64(U), int(direction), gamma, F)
+    return F
+
+
+def wave_speeds(U, direction, gamma=5.0 / 3.0):
+    cf, ca, cs = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_wave_speeds(_f64(U), int(direction), gamma, C.byref(cf), C.byref(ca), C.byref(cs))
+    return cf.value, ca.value, cs.value
+
+
+def eigensystem(Wn, gamma=5.0 / 3.0):
+    """Sweep-frame eigen-system at primitive state Wn -> (lam[8], L[8,8], R[8,8])."""
+    lam = np.zeros(8)
+    L = np.zeros(64)
+    R = np.zeros(64)
+    lib().orc_eigensystem(_f64(Wn), gamma, lam, L, R)
+    return lam, L.reshape(8, 8), R.reshape(8, 8)
+
+
+def interface_flux(Us, gamma=5.0 / 3.0, eps=1e-6):
+    F = np.zeros(8)
+    lib().orc_interface_flux(_f64(np.asarray(Us).reshape(48)), gamma, eps, F)
+    return F
+
+
+# ---- grid operations ----
+def _state(grid: Grid, u):
+    if u.shape != grid.shape or u.dtype != np.float64 or not u.flags.c_contiguous:
+        raise ValueError(f"state must be C-contiguous float64 {grid.shape}, got {u.shape} {u.dtype}")
+    return u
+
+
+def fill_ghosts(grid: Grid, u):
+    g = grid.c()
+    lib().orc_fill_ghosts(C.byref(g), _state(grid, u).reshape(-1))
+    return u
+
+
+def rhs(grid: Grid, u):
+    g = grid.c()
+    out = np.zeros(grid.shape)
+    rc = lib().orc_rhs(C.byref(g), _state(grid, u).reshape(-1), out.reshape(-1))
+    if rc != 0:
+        raise FloatingPointError("oracle rhs: non-physical state")
+    return out
+
+
+def cfl_dt(grid: Grid, u):
+    g = grid.c()
+    dt = lib().orc_cfl_dt(C.byref(g), _state(grid, u).reshape(-1))
+    if dt <= 0:
+        raise FloatingPointError("oracle cfl_dt: non-physical state")
+    return dt
+
+
+def rk4_step(grid: Grid, u, dt):
+    g = grid.c()
+    rc = lib().orc_rk4_step(C.byref(g), _state(grid, u).reshape(-1), float(dt))
+    if rc != 0:
+        raise FloatingPointError("oracle rk4_step: non-physical state")
+    return u
+
+
+def sums(grid: Grid, u):
+    g = grid.c()
+    out = np.zeros(8)
+    lib().orc_sums(C.byref(g), _state(grid, u).reshape(-1), out)
+    return out
+
+
+def divb(grid: Grid, u):
+    g = grid.c()
+    mx, l1 = C.c_double(), C.c_double()
+    lib().orc_divb(C.byref(g), _state(grid, u).reshape(-1), C.byref(mx), C.byref(l1))
+    return mx.value, l1.value

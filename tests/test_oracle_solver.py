@@ -1,0 +1,341 @@
+"""Solver-level pins of the oracle (arXiv:1808.10633 Sec. 2.1-2.2, Sec. 3.1):
+ghost zones, time step, conservation, corner div B, fifth-order convergence
+of the four linear waves, fourth-order RK in time, rotational invariance of
+the unsplit sweeps + CT, an exact Euler Riemann solution (B = 0), the
+Brio-Wu wave structure and a CT advection problem with an exact solution."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1808_10633_amd import inputs as I
+
+G53 = 5.0 / 3.0
+
+
+def grid3(orc, nx, ny, nz, **kw):
+    return orc.Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, 1.0 / nz, **kw)
+
+
+def run_to(orc, g, u, T, dt_fixed=None):
+    t = 0.0
+    while t < T - 1e-14:
+        dt = dt_fixed if dt_fixed else orc.cfl_dt(g, u)
+        dt = min(dt, T - t)
+        orc.rk4_step(g, u, dt)
+        t += dt
+    return u
+
+
+def random_smooth(nx, ny, nz, seed, amp=0.1):
+    """Smooth random state (a few low Fourier modes per field)."""
+    rng = np.random.default_rng(seed)
+    x = [(np.arange(n) + 0.5) / n for n in (nx, ny, nz)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    prim = []
+    base = [1.0, 0.2, -0.1, 0.15, 0.7, 0.4, -0.3, 1.0]
+    for q in range(8):
+        f = np.full(X.shape, base[q])
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            f = f + amp * rng.normal() * np.cos(2 * math.pi * (k[0] * X + k[1] * Y + k[2] * Z) + rng.uniform(0, 6))
+        prim.append(f)
+    rho, vx, vy, vz, bx, by, bz, p = prim
+    u = I.conserved(rho, [vx, vy, vz], [bx, by, bz], p, G53)
+    out = np.zeros(I.padded_shape(nx, ny, nz))
+    out[I.interior_slices(nx, ny, nz)] = u
+    return out
+
+
+# ---------------------------------------------------------------- ghosts, dt
+
+def test_ghost_fill_periodic_and_outflow(orc):
+    g = orc.Grid(5, 4, 1, bc=(0, 0, 1, 1, 0, 0))
+    u = np.zeros(g.shape)
+    rng = np.random.default_rng(0)
+    g.interior(u)[...] = rng.normal(size=g.interior(u).shape)
+    orc.fill_ghosts(g, u)
+    core = u[:, 0, 3:7, 3:8]
+    # periodic in x: ghost i=-1 equals interior i=4
+    assert np.array_equal(u[:, 0, 3:7, 2], core[:, :, 4])
+    assert np.array_equal(u[:, 0, 3:7, 8], core[:, :, 0])
+    # outflow in y: copies of the first/last interior row, including x ghosts
+    assert np.array_equal(u[:, 0, 0, :], u[:, 0, 3, :])
+    assert np.array_equal(u[:, 0, 9, :], u[:, 0, 6, :])
+
+
+def test_cfl_closed_form(orc):
+    # v = 0, B along x: fast speed max(a, c_A) along x, sqrt(a^2 + c_A^2)
+    # across; dt = C / sum_d c_f,d / dx_d.
+    nx, ny, nz = 6, 5, 4
+    g = orc.Grid(nx, ny, nz, 0.1, 0.2, 0.3, cfl=0.4)
+    rho, p, bx = 1.3, 0.7, 0.9
+    u = np.zeros(g.shape)
+    Ui = orc.prim_to_cons(np.array([rho, 0, 0, 0, bx, 0, 0, p]))
+    g.interior(u)[...] = Ui[:, None, None, None]
+    a2, ca2 = G53 * p / rho, bx * bx / rho
+    want = 0.4 / (math.sqrt(max(a2, ca2)) / 0.1 + math.sqrt(a2 + ca2) / 0.2 + math.sqrt(a2 + ca2) / 0.3)
+    assert abs(orc.cfl_dt(g, u) - want) < 1e-15 * want
+    g.interior(u)[0, 1, 1, 1] = -1.0
+    with pytest.raises(FloatingPointError):
+        orc.cfl_dt(g, u)
+
+
+# ------------------------------------------------------- invariants (3-D)
+
+def test_conservation_periodic(orc):
+    n = 12
+    g = grid3(orc, n, n, n)
+    u = I.turbulence((n, n, n), mach=1.0, beta=10.0, seed=7, kmax=5).numpy().copy()
+    s0 = orc.sums(g, u)
+    for _ in range(2):
+        orc.rk4_step(g, u, orc.cfl_dt(g, u))
+    s1 = orc.sums(g, u)
+    scale = np.abs(g.interior(u)).reshape(8, -1).max(1) * n ** 3
+    assert (np.abs(s1 - s0) / scale).max() < 1e-14, (s1 - s0) / scale
+
+
+def test_divb_vector_potential_stays_zero(orc):
+    n = 10
+    g = grid3(orc, n, n, n)
+    u = I.turbulence((n, n, n), mach=0.8, beta=1.0, seed=3, kmax=4).numpy().copy()
+    bscale = np.abs(g.interior(u)[4:7]).max() * n
+    m0, _ = orc.divb(g, u)
+    assert m0 < 1e-13 * bscale
+    for _ in range(2):
+        orc.rk4_step(g, u, orc.cfl_dt(g, u))
+    m1, _ = orc.divb(g, u)
+    assert m1 < 1e-13 * bscale
+
+
+def _corner_div_field(g, u, orc):
+    """Corner divergence field by an independent numpy formula."""
+    v = u.copy()
+    orc.fill_ghosts(g, v)
+    B = v[4:7]
+    out = 0.0
+    sl = lambda a, b, c: B[:, 3 + c:3 + c + g.nz, 3 + b:3 + b + g.ny, 3 + a:3 + a + g.nx]
+    cells = {(a, b, c): sl(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)}
+    dx = sum(cells[(1, b, c)][0] - cells[(0, b, c)][0] for b in (0, 1) for c in (0, 1)) / 4 / g.dx
+    dy = sum(cells[(a, 1, c)][1] - cells[(a, 0, c)][1] for a in (0, 1) for c in (0, 1)) / 4 / g.dy
+    dz = sum(cells[(a, b, 1)][2] - cells[(a, b, 0)][2] for a in (0, 1) for b in (0, 1)) / 4 / g.dz
+    return dx + dy + dz
+
+
+def test_divb_discrete_invariant_with_nonzero_divergence(orc):
+    # CT leaves the corner divergence unchanged whatever its initial value.
+    n = 8
+    g = grid3(orc, n, n, n)
+    u = random_smooth(n, n, n, seed=5)
+    rng = np.random.default_rng(9)
+    g.interior(u)[4:7] += 1e-3 * rng.normal(size=g.interior(u)[4:7].shape)
+    d0 = _corner_div_field(g, u, orc)
+    assert np.abs(d0).max() > 1e-3
+    m0, l10 = orc.divb(g, u)
+    assert abs(m0 - np.abs(d0).max()) < 1e-12 and abs(l10 - np.abs(d0).mean()) < 1e-12
+    orc.rk4_step(g, u, orc.cfl_dt(g, u))
+    d1 = _corner_div_field(g, u, orc)
+    assert np.abs(d1 - d0).max() < 1e-14 * np.abs(d0).max()
+
+
+def test_rotational_invariance_of_sweeps_and_ct(orc):
+    # Relabelling the axes cyclically (x->y->z->x) and the components with
+    # them must give the relabelled solution, up to summation order.
+    nx, ny, nz = 6, 7, 8
+    u = random_smooth(nx, ny, nz, seed=2)
+    g = orc.Grid(nx, ny, nz, 0.1, 0.12, 0.15)
+    # rotated problem: new x = old z, new y = old x, new z = old y
+    # ur[v][k'][j'][i'] with i' = old k, j' = old i, k' = old j
+    ur = np.ascontiguousarray(np.transpose(u, (0, 2, 3, 1)))
+    comp = [0, 3, 1, 2, 6, 4, 5, 7]     # new (mx,my,mz) = old (mz,mx,my); same for B
+    ur = np.ascontiguousarray(ur[comp])
+    gr = orc.Grid(nz, nx, ny, 0.15, 0.1, 0.12)
+    du = orc.rhs(g, u)
+    dur = orc.rhs(gr, ur)
+    inv = np.argsort(comp)
+    back = np.transpose(dur, (0, 3, 1, 2))[inv]
+    a = g.interior(du)
+    b = back[:, 3:3 + nz, 3:3 + ny, 3:3 + nx]
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+# ------------------------------------------------- convergence (Sec. 3.1)
+
+@pytest.mark.parametrize("family,amp", [("alfven", 1e-5), ("entropy", 1e-5),
+                                        ("fast", 1e-7), ("slow", 1e-7)])
+def test_linear_wave_fifth_order(orc, family, amp):
+    # Sec. 3.1: the four 1-D linear waves converge at fifth order.  Fast and
+    # slow waves use a smaller amplitude so that steepening (an O(amp^2)
+    # nonlinear effect the paper names) stays below the truncation error.
+    errs = []
+    for n in (16, 32, 64):
+        u, speed = I.linear_wave_1d(family, n, amp=amp)
+        g = orc.Grid(n, dx=1.0 / n, cfl=0.4)
+        run_to(orc, g, u, 1.0 / abs(speed))
+        ue, _ = I.linear_wave_1d(family, n, amp=amp, t=1.0 / abs(speed))
+        e = np.abs(g.interior(u) - g.interior(ue)).mean(axis=(1, 2, 3))
+        errs.append(math.sqrt((e ** 2).sum()))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert (order > 4.7).all(), (errs, order)
+    assert errs[-1] < 2e-11 * (amp / 1e-5) * 10
+
+
+def test_rk4_fourth_order_in_time(orc):
+    # Fixed grid, dt halved: differences between successive solutions shrink
+    # by 2^4 (classical four-stage, fourth-order RK, Sec. 2.1).
+    n = 24
+    sols = []
+    for nsteps in (8, 16, 32):
+        u, speed = I.linear_wave_1d("fast", n, amp=1e-2)
+        g = orc.Grid(n, dx=1.0 / n)
+        T = 0.25
+        run_to(orc, g, u, T, dt_fixed=T / nsteps)
+        sols.append(g.interior(u).copy())
+    r = np.abs(sols[0] - sols[1]).max() / np.abs(sols[1] - sols[2]).max()
+    assert 14.0 < r < 18.5, r
+
+
+# ------------------------------------------------------- shock tubes
+
+def exact_euler_riemann(WL, WR, gamma, xi):
+    """Exact solution of the 1-D Euler Riemann problem (two-rarefaction /
+    shock relations, pressure found by bisection), sampled at x/t = xi."""
+    rL, uL, pL = WL
+    rR, uR, pR = WR
+    aL, aR = math.sqrt(gamma * pL / rL), math.sqrt(gamma * pR / rR)
+
+    def fk(p, r, pk, ak):
+        if p > pk:
+            A, B = 2 / ((gamma + 1) * r), (gamma - 1) / (gamma + 1) * pk
+            return (p - pk) * math.sqrt(A / (p + B))
+        return 2 * ak / (gamma - 1) * ((p / pk) ** ((gamma - 1) / (2 * gamma)) - 1)
+
+    lo, hi = 1e-12, 100 * max(pL, pR)
+    for _ in range(200):
+        m = 0.5 * (lo + hi)
+        if fk(m, rL, pL, aL) + fk(m, rR, pR, aR) + uR - uL > 0:
+            hi = m
+        else:
+            lo = m
+    ps = 0.5 * (lo + hi)
+    us = 0.5 * (uL + uR) + 0.5 * (fk(ps, rR, pR, aR) - fk(ps, rL, pL, aL))
+    g1 = (gamma - 1) / (gamma + 1)
+    out = np.zeros((3, len(xi)))
+    for n, s in enumerate(xi):
+        if s < us:
+            r, u, p, a = rL, uL, pL, aL
+            sgn = 1
+        else:
+            r, u, p, a = rR, uR, pR, aR
+            sgn = -1
+        # work in the frame where the wave is on the left (mirror the right)
+        s_ = sgn * s
+        u_ = sgn * u
+        us_ = sgn * us
+        if ps > p:
+            S = u_ - a * math.sqrt((gamma + 1) / (2 * gamma) * ps / p + (gamma - 1) / (2 * gamma))
+            if s_ < S:
+                W = (r, u_, p)
+            else:
+                W = (r * (ps / p + g1) / (g1 * ps / p + 1), us_, ps)
+        else:
+            SH = u_ - a
+            ast = a * (ps / p) ** ((gamma - 1) / (2 * gamma))
+            ST = us_ - ast
+            if s_ < SH:
+                W = (r, u_, p)
+            elif s_ > ST:
+                W = (r * (ps / p) ** (1 / gamma), us_, ps)
+            else:
+                uu = 2 / (gamma + 1) * (a + (gamma - 1) / 2 * u_ + s_)
+                aa = 2 / (gamma + 1) * (a + (gamma - 1) / 2 * (u_ - s_))
+                W = (r * (aa / a) ** (2 / (gamma - 1)), uu, p * (aa / a) ** (2 * gamma / (gamma - 1)))
+        out[:, n] = (W[0], sgn * W[1], W[2])
+    return out
+
+
+def test_sod_matches_exact_euler_solution(orc):
+    # B = 0 reduces the system to gas dynamics; the triple-degenerate
+    # eigenvector conventions are exercised at every interface.
+    gamma, T = 1.4, 0.2
+    errs = []
+    for n in (100, 200):
+        u = I.sod(n, gamma)
+        g = orc.Grid(n, dx=1.0 / n, gamma=gamma, cfl=0.4, bc=(1, 1, 0, 0, 0, 0))
+        run_to(orc, g, u, T)
+        x = (np.arange(n) + 0.5) / n
+        ex = exact_euler_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma, (x - 0.5) / T)
+        rho = g.interior(u)[0, 0, 0]
+        errs.append(np.abs(rho - ex[0]).mean())
+        assert rho.min() > 0.1 and rho.max() < 1.01
+    assert errs[0] < 1.2e-2 and errs[1] < 0.7 * errs[0], errs
+
+
+def test_brio_wu_wave_structure(orc):
+    # Brio & Wu shock tube (gamma = 2): B_y reverses sign once across the
+    # compound wave/contact region, states outside the fast fans are
+    # untouched, the solution stays physical, sum B_y is conserved.
+    n, T = 400, 0.1
+    u = I.brio_wu(n)
+    g = orc.Grid(n, dx=1.0 / n, gamma=2.0, cfl=0.4, bc=(1, 1, 0, 0, 0, 0))
+    sb0 = orc.sums(g, u)
+    run_to(orc, g, u, T)
+    q = g.interior(u)[:, 0, 0, :]
+    W = np.array([orc.cons_to_prim(q[:, i], 2.0) for i in range(n)]).T
+    rho, by, p = W[0], W[5], W[7]
+    assert rho.min() > 0.05 and p.min() > 0.0
+    assert abs(orc.sums(g, u)[5] - sb0[5]) < 1e-12 * n
+    s = np.sign(by[np.abs(by) > 0.05])
+    assert np.count_nonzero(np.diff(s)) == 1
+    x = (np.arange(n) + 0.5) / n
+    u0 = I.brio_wu(n)
+    cfl_, _, _ = orc.wave_speeds(u0[:, 0, 0, 3], 0, 2.0)
+    cfr, _, _ = orc.wave_speeds(u0[:, 0, 0, 3 + n - 1], 0, 2.0)
+    assert np.abs(rho[x < 0.5 - cfl_ * T - 0.05] - 1.0).max() < 1e-6
+    assert np.abs(rho[x > 0.5 + cfr * T + 0.05] - 0.125).max() < 1e-6
+
+
+# ------------------------------------------------ CT with an exact solution
+
+def _advected_field(n, t, vel=(1.0, 0.5)):
+    """Weak 2-D field from A_z = A0 sin(2pi x) sin(2pi y)/(2pi), carried by a
+    uniform flow; the exact solution is the shifted pattern."""
+    x = (np.arange(n) + 0.5) / n
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    Xs, Ys = X - vel[0] * t, Y - vel[1] * t
+    A0 = 1e-3
+    bx = A0 * np.sin(2 * math.pi * Xs) * np.cos(2 * math.pi * Ys)
+    by = -A0 * np.cos(2 * math.pi * Xs) * np.sin(2 * math.pi * Ys)
+    one = np.ones_like(X)
+    u = I.conserved(one, [vel[0] * one, vel[1] * one, 0 * one], [bx, by, 0 * one], one, G53)
+    out = np.zeros(I.padded_shape(n, n, 1))
+    out[I.interior_slices(n, n, 1)] = u.reshape(8, 1, n, n)
+    return out
+
+
+def test_ct_advection_converges(orc):
+    errs = []
+    T = 0.1
+    for n in (16, 32):
+        u = _advected_field(n, 0.0)
+        g = orc.Grid(n, n, 1, 1.0 / n, 1.0 / n, 1.0)
+        run_to(orc, g, u, T)
+        ue = _advected_field(n, T)
+        errs.append(np.abs(g.interior(u)[4:6] - g.interior(ue)[4:6]).mean())
+    order = math.log2(errs[0] / errs[1])
+    assert order > 1.8, (errs, order)
+    assert errs[1] < 5e-6
+
+
+def test_inclined_alfven_wave_accuracy(orc):
+    # The 3-D inclined Alfven wave (amplitude 1e-6) stays close to the exact
+    # shifted wave over a few steps; CT limits B to second order (Sec. 2.1).
+    errs = []
+    for n in (8, 16):
+        u, ca = I.alfven_wave_3d(n)
+        g = grid3(orc, n, n, n)
+        T = 0.02
+        run_to(orc, g, u, T)
+        ue, _ = I.alfven_wave_3d(n, t=T)
+        errs.append(np.abs(g.interior(u) - g.interior(ue)).max())
+    assert errs[1] < errs[0] / 3.5 and errs[1] < 1e-8, errs
