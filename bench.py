@@ -1,0 +1,115 @@
+"""Benchmark of the WENO5-MHD stage library on one MI355X.
+
+Workload: decaying MHD turbulence in a periodic 512^3 box (rms Mach 1.0,
+plasma beta 100, gamma 5/3, the turbulence generator of the precision-form
+configuration), advanced with full FP64 RK4 steps (CFL time step, 4 stages of
+ghost fill + x/y/z characteristic WENO sweeps + flux difference/CT/RK update)
+through the C ABI.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: zone-stage updates/s over `--steps` timed steps, the
+roofline of the dominant kernel (the characteristic sweep, VALU-bound, FP64
+vector peak) from HIP-event kernel timings, and the serial CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-stage updates/s (WENO5-MHD 512^3) FP64 vs FP32/learned at stated L1 err; %HBM"
+
+# Algorithmic work of one interface of the characteristic sweep (FP64 ops,
+# one fused multiply-add counted as 2 flops), and the FP64 vector peak.
+FLOP_PER_INTERFACE = None   # filled from paper_1808_10633_amd.opcount
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=64)
+    return ap.parse_args()
+
+
+def cpu_baseline(n):
+    """Serial FP64 oracle: one full RK4 step of the same turbulence recipe on
+    an n^3 box (a bounded sample of the 512^3 workload)."""
+    from oracle import oracle
+    from paper_1808_10633_amd import inputs
+    u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003).numpy().copy()
+    g = oracle.Grid(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, cfl=0.4)
+    t0 = time.perf_counter()
+    dt = oracle.cfl_dt(g, u)
+    oracle.rk4_step(g, u, dt)
+    el = time.perf_counter() - t0
+    return {"value": n ** 3 * 4 / el, "unit": "zone-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RK4 step (4 stages) of the {n}^3 box of the same turbulence recipe, "
+                      f"serial C oracle, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU path is a "
+              "design (halo-exchanged bricks), not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1808_10633_amd import inputs, opcount, wombat
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = a.n
+    u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")
+    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP64, cfl=0.4)
+    print(f"[bench] {n}^3 FP64 turbulence ready; warmup {a.warmup}", file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        ctx.step(u, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ctx.step(u, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(f"[bench] {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+    zs = n ** 3 * 4 * a.steps / el
+
+    # dominant kernel: the characteristic sweeps; HIP events on the library stream
+    ms = ctx.time_kernels(u, reps=5)
+    nface = [(n + 1) * (n + 2) * (n + 2)] * 3
+    fpi = opcount.flops_per_interface()
+    sweep_ms = ms[2]      # y sweep (x and z reported beside it)
+    achieved = fpi * nface[1] / (sweep_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "sweep_kernel<1,double> (y sweep)",
+            "flop_per_interface": fpi, "interfaces_per_launch": nface[1],
+            "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
+                          "update": ms[4]}}
+    out = {"metric": METRIC, "value": zs, "unit": "zone-stage updates/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": el / a.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"decaying MHD turbulence {n}^3 periodic, rms Mach 1.0, beta 100, "
+                                  "gamma 5/3, FP64 characteristic WENO5 + CT + RK4, CFL 0.4 step",
+                      "n": n, "precision": "fp64"},
+           "roofline": roof}
+    del ctx, u
+    torch.cuda.empty_cache()
+    if not a.no_cpu:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * wombat_weno.h -- C ABI of the MI355X (gfx950) WENO5 ideal-MHD stage library.
+ *
+ * The library advances the eight conserved ideal-MHD variables with the
+ * fifth-order characteristic WENO finite-difference scheme of Donnert et al.,
+ * "Towards Exascale Simulations of the ICM Dynamo with WENO-Wombat"
+ * (arXiv:1808.10633), Sec. 2.1:
+ *   - per sweep direction, the interface flux of each characteristic field by
+ *     eq. (1), with the WENO5 interpolant of eq. (2), the nonlinear weights of
+ *     eqs. (3)-(4) (epsilon = 1e-6) and the smoothness indicators of
+ *     eqs. (5)-(7), after a Roe-type decoupling of the 8 PDEs and a
+ *     Lax-Friedrichs flux splitting;
+ *   - flux differences in x, y and z (Sec. 2.2: unsplit sweeps, one final
+ *     update), constrained transport of B on a staggered mesh (Sec. 2.1),
+ *   - a four-stage, fourth-order Runge-Kutta integrator (Sec. 2.1),
+ *   - 3 ghost zones per side (Sec. 2.2).
+ * The paper leaves the eigenvectors, the interface mean state, the CT edge
+ * average and the time-step rule to unpublished work; this library uses:
+ * the arithmetic mean of the primitive variables of the two cells, the
+ * seven-wave eigenvectors with the Roe-Balsara normalisation (normal field
+ * held fixed, zero normal-field flux), the local per-field Lax-Friedrichs
+ * speed max|lambda^s| over the six stencil cells, the four-face mean of the
+ * transverse-field fluxes as edge EMF with the cell field advanced by the
+ * mean of its two face updates, classical RK4, and
+ * dt = C / max_cells sum_d (|v_d| + c_f,d)/dx_d.  Units: Heaviside-Lorentz
+ * (magnetic pressure B^2/2), ideal-gas equation of state.
+ *
+ * STATE LAYOUT (every state argument):
+ *   caller-owned device memory, contiguous, u[v][k][j][i] with i fastest;
+ *   v = 0..7 = (rho, rho vx, rho vy, rho vz, Bx, By, Bz, E);
+ *   dims (nx+2gx) x (ny+2gy) x (nz+2gz), g = 3 on an axis with n > 1 and
+ *   g = 0 on an inactive axis (n = 1); point values at cell centres.
+ *   Element type: double for WW_FP64, float for WW_FP32_MIXED.
+ *   A 256-byte aligned base is recommended, 8-byte alignment is required.
+ *
+ * ERRORS: every call returns WW_OK (0) or a negative ww_status.  Invalid
+ * arguments are reported before any device work and leave no side effect.
+ * A HIP failure makes the context's error sticky: later calls return
+ * WW_ERR_HIP until wombat_weno_destroy.  No C++ exception crosses the ABI.
+ * wombat_weno_last_error(ctx) gives a message for the last failure
+ * (wombat_weno_last_error(NULL) for failures of wombat_weno_init).
+ *
+ * THREADING AND ORDERING: a context is used by one host thread at a time;
+ * several contexts may coexist.  All device work of a context is enqueued on
+ * the stream given in the configuration (0 = the null stream), in call
+ * order.  Calls documented as synchronous wait for that stream.  The library
+ * allocates device memory only in wombat_weno_init and frees it only in
+ * wombat_weno_destroy; it never frees caller memory.
+ */
+#ifndef WOMBAT_WENO_H
+#define WOMBAT_WENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WOMBAT_WENO_ABI_VERSION 1
+
+typedef enum {
+    WW_OK = 0,
+    WW_ERR_INVALID_ARG = -1,  /* bad pointer, size, alias or configuration   */
+    WW_ERR_UNSUPPORTED = -2,  /* valid request this build does not provide   */
+    WW_ERR_OOM = -3,          /* device allocation failed in init            */
+    WW_ERR_HIP = -4,          /* a HIP runtime call failed (sticky)          */
+    WW_ERR_NONPHYSICAL = -5,  /* rho <= 0, p <= 0 or a non-finite value      */
+    WW_ERR_USER_BC = -6,      /* a user boundary callback returned non-zero  */
+    WW_ERR_STATE = -7         /* call not allowed in the context's state     */
+} ww_status;
+
+typedef enum { WW_FP64 = 0, WW_FP32_MIXED = 1 } ww_precision;
+typedef enum { WW_BC_PERIODIC = 0, WW_BC_OUTFLOW = 1, WW_BC_USER = 2 } ww_bc;
+
+/* User boundary hook: called for each WW_BC_USER face (0..5 = -x,+x,-y,+y,
+ * -z,+z) whenever ghosts are filled, after the built-in faces of the same
+ * axis.  It must enqueue its device work on `stream` (a hipStream_t) and fill
+ * the 3-deep ghost slab of that face for all 8 variables; return 0 on
+ * success. */
+typedef int (*ww_user_bc_fn)(void *user, void *d_u, int face, void *stream);
+
+typedef struct {
+    int nx, ny, nz;          /* interior cells, >= 1; 1 marks an inactive axis;
+                                an active axis needs n >= 3                    */
+    int ng;                  /* ghost cells per side on active axes: must be 3 */
+    double dx, dy, dz;       /* cell widths, > 0                               */
+    double gamma;            /* ratio of specific heats, > 1                   */
+    double cfl;              /* Courant number in (0, 1]                       */
+    double eps;              /* WENO epsilon of eq. (4), > 0 (paper: 1e-6)     */
+    int precision;           /* ww_precision                                   */
+    int bc[6];               /* ww_bc per face -x,+x,-y,+y,-z,+z; periodic
+                                must be set on both faces of an axis           */
+    ww_user_bc_fn user_bc;   /* required if any face is WW_BC_USER             */
+    void *user_bc_ctx;       /* passed back to user_bc                         */
+    void *stream;            /* hipStream_t for all work; NULL = null stream   */
+    int device;              /* HIP device ordinal                             */
+} wombat_weno_config;
+
+typedef struct wombat_weno wombat_weno_t;
+
+/* ABI version of the loaded library (WOMBAT_WENO_ABI_VERSION). */
+int wombat_weno_abi_version(void);
+
+/* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
+ * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0.
+ * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
+int wombat_weno_config_default(wombat_weno_config *cfg);
+
+/* Check a configuration without touching any device.  WW_OK or
+ * WW_ERR_INVALID_ARG (message in wombat_weno_last_error(NULL)). */
+int wombat_weno_validate_config(const wombat_weno_config *cfg);
+
+/* Number of elements (not bytes) of one padded state array. */
+int64_t wombat_weno_state_elems(const wombat_weno_config *cfg);
+
+/* Create a context: validates cfg, selects cfg->device and allocates every
+ * device buffer the library will use (three state-sized work arrays, the face
+ * fluxes of the three sweeps and small reduction buffers).  *out is written
+ * only on success.  Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP. */
+int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out);
+
+/* Release a context and its device memory.  NULL is allowed. */
+void wombat_weno_destroy(wombat_weno_t *ctx);
+
+/* Message of the last failure on ctx (NULL: of the last failed init or
+ * validation on this thread).  The string is owned by the library. */
+const char *wombat_weno_last_error(const wombat_weno_t *ctx);
+
+/* Fill the 3-deep ghost zones of d_u (periodic copy, zero-gradient outflow
+ * or the user hook), axis by axis (Sec. 2.2).  Asynchronous. */
+int wombat_weno_fill_ghosts(wombat_weno_t *ctx, void *d_u);
+
+/* CFL time step dt = cfl / max over interior cells of
+ * sum_d (|v_d| + c_f,d)/dx_d, reduced in FP64 on the device; waits for the
+ * stream and writes *dt.  WW_ERR_NONPHYSICAL if any interior cell has
+ * rho <= 0, p <= 0 or a non-finite value (then *dt is not written). */
+int wombat_weno_cfl_dt(wombat_weno_t *ctx, const void *d_u, double *dt);
+
+/* As wombat_weno_cfl_dt but asynchronous: writes dt (double) to device
+ * memory d_dt and, to d_flag (int32, device), 0 or the number of
+ * non-physical cells (dt is then not meaningful). */
+int wombat_weno_cfl_dt_device(wombat_weno_t *ctx, const void *d_u, double *d_dt,
+                              int32_t *d_flag);
+
+/* Semi-discrete right-hand side L(U) of Sec. 2.1: fills the ghosts of d_u,
+ * runs the x, y, z characteristic WENO sweeps, differences the fluxes of
+ * rho, m, E and advances B by constrained transport; writes L(U) into the
+ * interior of d_dudt (ghosts of d_dudt untouched).  d_dudt must not alias
+ * d_u.  Asynchronous. */
+int wombat_weno_rhs(wombat_weno_t *ctx, void *d_u, void *d_dudt);
+
+/* One Runge-Kutta stage s in {0,1,2,3} of the classical RK4 step of size dt
+ * (Sec. 2.1), in the low-storage form
+ *   s=0: acc = u0 + dt/6 L(u0),   out = u0 + dt/2 L(u0)   (pass us_in == u0)
+ *   s=1: acc += dt/3 L(us),       out = u0 + dt/2 L(us)
+ *   s=2: acc += dt/3 L(us),       out = u0 + dt   L(us)
+ *   s=3:                          out = acc + dt/6 L(us)   (u0 unused)
+ * Ghosts of d_us_in are filled first; interior cells of d_acc and d_us_out
+ * are written.  d_us_out may alias d_u0 (pointwise), but not d_us_in or
+ * d_acc.  dt must be finite and > 0.  Asynchronous. */
+int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0,
+                      void *d_us_in, void *d_acc, void *d_us_out);
+
+/* A full RK4 step of d_u in place using the context's work arrays.
+ * dt <= 0 computes the CFL step first (synchronous; may return
+ * WW_ERR_NONPHYSICAL).  *dt_used (may be NULL) receives the step taken.
+ * Asynchronous when dt > 0. */
+int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used);
+
+/* FP64 sums of the 8 conserved variables over the interior cells (fixed
+ * reduction order, deterministic).  Synchronous. */
+int wombat_weno_sums(wombat_weno_t *ctx, const void *d_u, double out[8]);
+
+/* Corner divergence of the cell-centred field: for each corner i+1/2 (and
+ * j+1/2, k+1/2 on active axes), i = 0..n-1, the sum over active axes d of the
+ * mean over the adjacent cell pairs of (B_d(+1) - B_d(0))/dx_d.  Fills the
+ * ghosts of d_u first.  Writes max |div B| and its mean.  Synchronous. */
+int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1);
+
+/* Kernel timing: average device time in milliseconds per launch of each
+ * kernel of one right-hand-side evaluation of d_u, measured with HIP events
+ * recorded on the context's stream around `reps` back-to-back launches
+ * (reps in 1..1000): ms[0] the ghost fill of all axes, ms[1..3] the x, y and
+ * z sweeps (0 for an inactive axis), ms[4] the flux-difference/CT/update
+ * kernel (writing L(U) into a work array).  d_u's ghosts are filled.
+ * Synchronous. */
+int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -104,6 +104,8 @@ def lib():
         L.orc_fill_ghosts.argtypes = [g, _dp]
         L.orc_rhs.argtypes = [g, _dp, _dp]
         L.orc_rhs.restype = C.c_int
+        L.orc_rhs_nofill.argtypes = [g, _dp, _dp]
+        L.orc_rhs_nofill.restype = C.c_int
         L.orc_cfl_dt.argtypes = [g, _dp]
         L.orc_cfl_dt.restype = d
         L.orc_rk4_step.argtypes = [g, _dp, d]
@@ -191,6 +193,16 @@ def rhs(grid: Grid, u):
     g = grid.c()
     out = np.zeros(grid.shape)
     rc = lib().orc_rhs(C.byref(g), _state(grid, u).reshape(-1), out.reshape(-1))
+    if rc != 0:
+        raise FloatingPointError("oracle rhs: non-physical state")
+    return out
+
+
+def rhs_nofill(grid: Grid, u):
+    """L(U) with the ghost zones of u taken as given (no refill)."""
+    g = grid.c()
+    out = np.zeros(grid.shape)
+    rc = lib().orc_rhs_nofill(C.byref(g), _state(grid, u).reshape(-1), out.reshape(-1))
     if rc != 0:
         raise FloatingPointError("oracle rhs: non-physical state")
     return out

@@ -499,14 +499,14 @@ static int nonphysical(const double U[8], double gamma)
 
 /* L(U): the semi-discrete right-hand side of one Runge-Kutta stage.
  * Returns 0, or -1 if a stencil cell is non-physical (rho<=0 or p<=0). */
-int orc_rhs(const orc_grid *gr, const double *uin, double *dudt)
+static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fill)
 {
     geom G = mkgeom(gr);
     long ntot = 8 * G.sv;
     double *u = (double *)malloc(sizeof(double) * ntot);
     int bad = 0;
     memcpy(u, uin, sizeof(double) * ntot);
-    orc_fill_ghosts(gr, u);
+    if (fill) orc_fill_ghosts(gr, u);
 
     faces FF[3];
     int d, e;
@@ -584,6 +584,18 @@ int orc_rhs(const orc_grid *gr, const double *uin, double *dudt)
     for (d = 0; d < 3; ++d) free(FF[d].f);
     free(u);
     return bad ? -1 : 0;
+}
+
+int orc_rhs(const orc_grid *gr, const double *u, double *dudt)
+{
+    return rhs_impl(gr, u, dudt, 1);
+}
+
+/* As orc_rhs, but the ghost zones of u are used as given (not refilled):
+ * L at a cell of a block cut out of a larger state with its ghosts. */
+int orc_rhs_nofill(const orc_grid *gr, const double *u, double *dudt)
+{
+    return rhs_impl(gr, u, dudt, 0);
 }
 
 /* dt = C / max over interior cells of sum_d (|v_d| + c_f,d) / dx_d.

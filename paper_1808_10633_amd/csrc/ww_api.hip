@@ -1,0 +1,503 @@
+// ww_api.hip -- the C ABI of include/wombat_weno.h: validation, context,
+// device memory, call order and error reporting.  All device work is
+// enqueued on the context's stream; no allocation happens after init.
+#include "../../include/wombat_weno.h"
+#include "ww_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+using ww::FaceBox;
+using ww::Geom;
+
+struct wombat_weno {
+    wombat_weno_config cfg;
+    Geom G;
+    FaceBox F[3];
+    size_t esize;          // bytes per state element
+    long elems;            // elements per state array
+    void *work[3];         // state-sized work arrays
+    void *ff[3];           // face fluxes per direction
+    double *part;          // reduction partials (nblk x 8)
+    int32_t *partflag;     // reduction flags (nblk)
+    double *dsmall;        // [0] dt, [1..8] sums / divb, flag at dflag
+    int32_t *dflag;
+    double *hsmall;        // pinned host mirror of dsmall (16 doubles + flag)
+    int nblk;
+    hipEvent_t ev[2];      // kernel timing
+    hipStream_t st;
+    int sticky;            // a HIP error happened: every later call fails
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail_ctx(wombat_weno_t *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg; else g_err = msg;
+    return code;
+}
+
+struct DevGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DevGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int hip_fail(wombat_weno_t *c, hipError_t e, const char *what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    if (c) { c->sticky = 1; c->err = buf; } else g_err = buf;
+    return WW_ERR_HIP;
+}
+
+#define WW_CHECK(ctx, call)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+int validate(const wombat_weno_config *c, std::string &why)
+{
+    if (!c) { why = "config is NULL"; return WW_ERR_INVALID_ARG; }
+    const int n[3] = { c->nx, c->ny, c->nz };
+    const double dl[3] = { c->dx, c->dy, c->dz };
+    int nact = 0;
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 1) { why = "cell counts must be >= 1"; return WW_ERR_INVALID_ARG; }
+        if (n[d] == 2) { why = "an active axis needs at least 3 cells"; return WW_ERR_INVALID_ARG; }
+        if (n[d] > (1 << 20)) { why = "cell count too large"; return WW_ERR_INVALID_ARG; }
+        if (!(dl[d] > 0.0) || !std::isfinite(dl[d])) { why = "cell widths must be finite and > 0"; return WW_ERR_INVALID_ARG; }
+        nact += n[d] > 1;
+    }
+    if (nact == 0) { why = "at least one axis must have more than one cell"; return WW_ERR_INVALID_ARG; }
+    if (c->ng != 3) { why = "ng must be 3"; return WW_ERR_INVALID_ARG; }
+    if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) { why = "gamma must be > 1"; return WW_ERR_INVALID_ARG; }
+    if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) { why = "cfl must be in (0, 1]"; return WW_ERR_INVALID_ARG; }
+    if (!(c->eps > 0.0) || !std::isfinite(c->eps)) { why = "eps must be finite and > 0"; return WW_ERR_INVALID_ARG; }
+    if (c->precision != WW_FP64 && c->precision != WW_FP32_MIXED) { why = "unknown precision"; return WW_ERR_INVALID_ARG; }
+    bool user = false;
+    for (int f = 0; f < 6; ++f) {
+        if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
+        user = user || c->bc[f] == WW_BC_USER;
+    }
+    for (int d = 0; d < 3; ++d)
+        if ((c->bc[2 * d] == WW_BC_PERIODIC) != (c->bc[2 * d + 1] == WW_BC_PERIODIC)) {
+            why = "periodic boundaries must be set on both faces of an axis";
+            return WW_ERR_INVALID_ARG;
+        }
+    if (user && !c->user_bc) { why = "a WW_BC_USER face needs user_bc"; return WW_ERR_INVALID_ARG; }
+    if (c->device < 0) { why = "device must be >= 0"; return WW_ERR_INVALID_ARG; }
+    return WW_OK;
+}
+
+long state_elems(const wombat_weno_config *c)
+{
+    const int n[3] = { c->nx, c->ny, c->nz };
+    long e = 8;
+    for (int d = 0; d < 3; ++d) e *= n[d] + (n[d] > 1 ? 6 : 0);
+    return e;
+}
+
+void make_geom(const wombat_weno_config *c, Geom &G, FaceBox F[3])
+{
+    const int n[3] = { c->nx, c->ny, c->nz };
+    const double dl[3] = { c->dx, c->dy, c->dz };
+    int N[3];
+    for (int d = 0; d < 3; ++d) {
+        G.n[d] = n[d];
+        G.act[d] = n[d] > 1;
+        G.g[d] = G.act[d] ? 3 : 0;
+        G.dl[d] = dl[d];
+        G.idl[d] = 1.0 / dl[d];
+        N[d] = n[d] + 2 * G.g[d];
+    }
+    G.s[0] = 1;
+    G.s[1] = N[0];
+    G.s[2] = (long)N[0] * N[1];
+    G.sv = (long)N[0] * N[1] * N[2];
+    G.base = G.g[0] + G.g[1] * G.s[1] + G.g[2] * G.s[2];
+    for (int d = 0; d < 3; ++d) {
+        FaceBox &B = F[d];
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) { B.lo[e] = 0; B.cnt[e] = n[e] + 1; }
+            else if (G.act[e]) { B.lo[e] = -1; B.cnt[e] = n[e] + 2; }
+            else { B.lo[e] = 0; B.cnt[e] = 1; }
+        }
+        B.s[0] = 1;
+        B.s[1] = B.cnt[0];
+        B.s[2] = (long)B.cnt[0] * B.cnt[1];
+        B.sc = (long)B.cnt[0] * B.cnt[1] * B.cnt[2];
+    }
+}
+
+// Test hook: WOMBAT_WENO_FAIL_ALLOC=k makes the k-th device allocation of
+// init fail (1-based), to exercise the out-of-memory path.
+int g_alloc_count = 0;
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    const char *f = getenv("WOMBAT_WENO_FAIL_ALLOC");
+    ++g_alloc_count;
+    if (f && atoi(f) == g_alloc_count) { *p = nullptr; return hipErrorOutOfMemory; }
+    return hipMalloc(p, bytes);
+}
+
+void release(wombat_weno_t *c)
+{
+    if (!c) return;
+    for (int i = 0; i < 3; ++i) { if (c->work[i]) (void)hipFree(c->work[i]); if (c->ff[i]) (void)hipFree(c->ff[i]); }
+    if (c->part) (void)hipFree(c->part);
+    if (c->partflag) (void)hipFree(c->partflag);
+    if (c->dsmall) (void)hipFree(c->dsmall);
+    if (c->hsmall) (void)hipHostFree(c->hsmall);
+    for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+}
+
+int precheck(wombat_weno_t *c)
+{
+    if (!c) return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "context is NULL");
+    if (c->sticky) return WW_ERR_HIP;
+    return WW_OK;
+}
+
+template <typename T>
+int fill_ghosts_t(wombat_weno_t *c, T *u)
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!c->G.act[ax]) continue;
+        WW_CHECK(c, ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
+        for (int side = 0; side < 2; ++side) {
+            int face = 2 * ax + side;
+            if (c->cfg.bc[face] != WW_BC_USER) continue;
+            int rc = c->cfg.user_bc(c->cfg.user_bc_ctx, u, face, (void *)c->st);
+            if (rc != 0) {
+                char buf[96];
+                snprintf(buf, sizeof buf, "user boundary hook returned %d on face %d", rc, face);
+                return fail_ctx(c, WW_ERR_USER_BC, buf);
+            }
+        }
+    }
+    return WW_OK;
+}
+
+// Ghosts + sweeps + update (mode 0: out = L(U); mode 1: RK stage).
+template <typename T>
+int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out, T *out,
+               const ww::StageCoef &k)
+{
+    int rc = fill_ghosts_t<T>(c, us);
+    if (rc) return rc;
+    ww::Phys P{ c->cfg.gamma, c->cfg.eps };
+    for (int d = 0; d < 3; ++d) {
+        if (!c->G.act[d]) continue;
+        WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->st));
+    }
+    WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, (const T *)c->ff[0],
+                                     (const T *)c->ff[1], (const T *)c->ff[2], c->F, c->G, k,
+                                     c->st));
+    return WW_OK;
+}
+
+template <typename T>
+int cfl_device_t(wombat_weno_t *c, const T *u, double *d_dt, int32_t *d_flag)
+{
+    WW_CHECK(c, ww::launch_cfl<T>(u, c->G, c->cfg.gamma, c->cfg.cfl, c->part, c->partflag,
+                                  c->nblk, d_dt, d_flag, c->st));
+    return WW_OK;
+}
+
+template <typename T>
+int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
+{
+    int rc = fill_ghosts_t<T>(c, u);
+    if (rc) return rc;
+    ww::Phys P{ c->cfg.gamma, c->cfg.eps };
+    ww::StageCoef k{ 0, 0, 0.0, 0.0 };
+    for (int which = 0; which < 5; ++which) {
+        ms[which] = 0.0;
+        if (which >= 1 && which <= 3 && !c->G.act[which - 1]) continue;
+        // one untimed launch, then `reps` timed ones
+        for (int r = 0; r <= reps; ++r) {
+            if (r == 1) WW_CHECK(c, hipEventRecord(c->ev[0], c->st));
+            if (which == 0) {
+                for (int ax = 0; ax < 3; ++ax)
+                    WW_CHECK(c, ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
+            } else if (which <= 3) {
+                int d = which - 1;
+                WW_CHECK(c, ww::launch_sweep<T>(d, u, (T *)c->ff[d], c->G, c->F[d], P, c->st));
+            } else {
+                WW_CHECK(c, ww::launch_update<T>(nullptr, nullptr, nullptr, (T *)c->work[0],
+                                                 (const T *)c->ff[0], (const T *)c->ff[1],
+                                                 (const T *)c->ff[2], c->F, c->G, k, c->st));
+            }
+        }
+        WW_CHECK(c, hipEventRecord(c->ev[1], c->st));
+        WW_CHECK(c, hipEventSynchronize(c->ev[1]));
+        float t = 0.0f;
+        WW_CHECK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
+        ms[which] = (double)t / reps;
+    }
+    return WW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wombat_weno_abi_version(void) { return WOMBAT_WENO_ABI_VERSION; }
+
+int wombat_weno_config_default(wombat_weno_config *cfg)
+{
+    if (!cfg) return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "config is NULL");
+    memset(cfg, 0, sizeof *cfg);
+    cfg->nx = cfg->ny = cfg->nz = 32;
+    cfg->ng = 3;
+    cfg->dx = cfg->dy = cfg->dz = 1.0 / 32.0;
+    cfg->gamma = 5.0 / 3.0;
+    cfg->cfl = 0.4;
+    cfg->eps = 1e-6;
+    cfg->precision = WW_FP64;
+    return WW_OK;
+}
+
+int wombat_weno_validate_config(const wombat_weno_config *cfg)
+{
+    std::string why;
+    int rc = validate(cfg, why);
+    if (rc) return fail_ctx(nullptr, rc, why);
+    return WW_OK;
+}
+
+int64_t wombat_weno_state_elems(const wombat_weno_config *cfg)
+{
+    std::string why;
+    if (validate(cfg, why) != WW_OK) return -1;
+    return state_elems(cfg);
+}
+
+int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
+{
+    std::string why;
+    if (!out) return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "out is NULL");
+    int rc = validate(cfg, why);
+    if (rc) return fail_ctx(nullptr, rc, why);
+    wombat_weno_t *c = new (std::nothrow) wombat_weno();
+    if (!c) return fail_ctx(nullptr, WW_ERR_OOM, "host allocation failed");
+    c->cfg = *cfg;
+    make_geom(cfg, c->G, c->F);
+    c->esize = cfg->precision == WW_FP64 ? sizeof(double) : sizeof(float);
+    c->elems = state_elems(cfg);
+    c->st = (hipStream_t)cfg->stream;
+    c->nblk = ww::cfl_blocks(c->G);
+    DevGuard dg(cfg->device);
+    if (!dg.ok) { delete c; return fail_ctx(nullptr, WW_ERR_HIP, "hipSetDevice failed"); }
+    g_alloc_count = 0;
+    auto oom = [&](const char *what) {
+        release(c);
+        delete c;
+        return fail_ctx(nullptr, WW_ERR_OOM, std::string("device allocation failed: ") + what);
+    };
+    for (int i = 0; i < 3; ++i)
+        if (dev_alloc(&c->work[i], c->esize * c->elems) != hipSuccess) return oom("work arrays");
+    for (int d = 0; d < 3; ++d)
+        if (c->G.act[d] && dev_alloc(&c->ff[d], c->esize * ww::NFC * c->F[d].sc) != hipSuccess)
+            return oom("face fluxes");
+    if (dev_alloc((void **)&c->part, sizeof(double) * 8 * c->nblk) != hipSuccess) return oom("partials");
+    if (dev_alloc((void **)&c->partflag, sizeof(int32_t) * c->nblk) != hipSuccess) return oom("flags");
+    if (dev_alloc((void **)&c->dsmall, sizeof(double) * 20) != hipSuccess) return oom("results");
+    c->dflag = (int32_t *)(c->dsmall + 16);
+    if (hipHostMalloc((void **)&c->hsmall, sizeof(double) * 20, hipHostMallocDefault) != hipSuccess) {
+        c->hsmall = nullptr;
+        return oom("pinned host buffer");
+    }
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+            c->ev[i] = nullptr;
+            release(c);
+            delete c;
+            return fail_ctx(nullptr, WW_ERR_HIP, "hipEventCreate failed");
+        }
+    *out = c;
+    return WW_OK;
+}
+
+void wombat_weno_destroy(wombat_weno_t *ctx)
+{
+    if (!ctx) return;
+    DevGuard dg(ctx->cfg.device);
+    if (!ctx->sticky) (void)hipStreamSynchronize(ctx->st);
+    release(ctx);
+    delete ctx;
+}
+
+const char *wombat_weno_last_error(const wombat_weno_t *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+int wombat_weno_fill_ghosts(wombat_weno_t *ctx, void *d_u)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_u is NULL");
+    DevGuard dg(ctx->cfg.device);
+    if (ctx->cfg.precision == WW_FP64) return fill_ghosts_t<double>(ctx, (double *)d_u);
+    return fill_ghosts_t<float>(ctx, (float *)d_u);
+}
+
+int wombat_weno_cfl_dt_device(wombat_weno_t *ctx, const void *d_u, double *d_dt, int32_t *d_flag)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !d_dt || !d_flag) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    DevGuard dg(ctx->cfg.device);
+    if (ctx->cfg.precision == WW_FP64) return cfl_device_t<double>(ctx, (const double *)d_u, d_dt, d_flag);
+    return cfl_device_t<float>(ctx, (const float *)d_u, d_dt, d_flag);
+}
+
+int wombat_weno_cfl_dt(wombat_weno_t *ctx, const void *d_u, double *dt)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !dt) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    DevGuard dg(ctx->cfg.device);
+    rc = ctx->cfg.precision == WW_FP64
+             ? cfl_device_t<double>(ctx, (const double *)d_u, ctx->dsmall, ctx->dflag)
+             : cfl_device_t<float>(ctx, (const float *)d_u, ctx->dsmall, ctx->dflag);
+    if (rc) return rc;
+    WW_CHECK(ctx, hipMemcpyAsync(ctx->hsmall, ctx->dsmall, sizeof(double) * 20,
+                                 hipMemcpyDeviceToHost, ctx->st));
+    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
+    int32_t flag = *(int32_t *)(ctx->hsmall + 16);
+    if (flag) {
+        char buf[96];
+        snprintf(buf, sizeof buf, "%d non-physical cells (rho<=0, p<=0 or non-finite)", (int)flag);
+        return fail_ctx(ctx, WW_ERR_NONPHYSICAL, buf);
+    }
+    *dt = ctx->hsmall[0];
+    return WW_OK;
+}
+
+int wombat_weno_rhs(wombat_weno_t *ctx, void *d_u, void *d_dudt)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !d_dudt) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    if (d_u == d_dudt) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_dudt must not alias d_u");
+    DevGuard dg(ctx->cfg.device);
+    ww::StageCoef k{ 0, 0, 0.0, 0.0 };
+    if (ctx->cfg.precision == WW_FP64)
+        return operator_t<double>(ctx, (double *)d_u, nullptr, nullptr, nullptr, (double *)d_dudt, k);
+    return operator_t<float>(ctx, (float *)d_u, nullptr, nullptr, nullptr, (float *)d_dudt, k);
+}
+
+int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0, void *d_us_in,
+                      void *d_acc, void *d_us_out)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (s < 0 || s > 3) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "stage must be 0..3");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (!d_us_in || !d_acc || !d_us_out || (s < 3 && !d_u0))
+        return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    if (d_us_out == d_us_in) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_us_out must not alias d_us_in");
+    if (d_acc == d_us_in || d_acc == d_us_out || (s < 3 && d_acc == d_u0))
+        return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_acc must not alias the other arrays");
+    DevGuard dg(ctx->cfg.device);
+    static const double bw[4] = { 1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 0.0 };
+    static const double cw[4] = { 0.5, 0.5, 1.0, 1.0 / 6.0 };
+    ww::StageCoef k{ 1, s, bw[s] * dt, cw[s] * dt };
+    if (ctx->cfg.precision == WW_FP64)
+        return operator_t<double>(ctx, (double *)d_us_in, (const double *)d_u0, (const double *)d_acc,
+                                  (double *)d_acc, (double *)d_us_out, k);
+    return operator_t<float>(ctx, (float *)d_us_in, (const float *)d_u0, (const float *)d_acc,
+                             (float *)d_acc, (float *)d_us_out, k);
+}
+
+int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_u is NULL");
+    if (!std::isfinite(dt)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "dt must be finite");
+    if (dt <= 0.0) {
+        rc = wombat_weno_cfl_dt(ctx, d_u, &dt);
+        if (rc) return rc;
+    }
+    void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
+    if ((rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A))) return rc;
+    if ((rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, B))) return rc;
+    if ((rc = wombat_weno_stage(ctx, 2, dt, d_u, B, acc, A))) return rc;
+    if ((rc = wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u))) return rc;
+    if (dt_used) *dt_used = dt;
+    return WW_OK;
+}
+
+int wombat_weno_sums(wombat_weno_t *ctx, const void *d_u, double out[8])
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !out) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    DevGuard dg(ctx->cfg.device);
+    if (ctx->cfg.precision == WW_FP64)
+        WW_CHECK(ctx, ww::launch_sums<double>((const double *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                              ctx->dsmall + 1, ctx->st));
+    else
+        WW_CHECK(ctx, ww::launch_sums<float>((const float *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                             ctx->dsmall + 1, ctx->st));
+    WW_CHECK(ctx, hipMemcpyAsync(ctx->hsmall, ctx->dsmall, sizeof(double) * 20,
+                                 hipMemcpyDeviceToHost, ctx->st));
+    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
+    for (int v = 0; v < 8; ++v) out[v] = ctx->hsmall[1 + v];
+    return WW_OK;
+}
+
+int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !max_abs || !l1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    if ((rc = wombat_weno_fill_ghosts(ctx, d_u))) return rc;
+    DevGuard dg(ctx->cfg.device);
+    if (ctx->cfg.precision == WW_FP64)
+        WW_CHECK(ctx, ww::launch_divb<double>((const double *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                              ctx->dsmall + 1, ctx->st));
+    else
+        WW_CHECK(ctx, ww::launch_divb<float>((const float *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                             ctx->dsmall + 1, ctx->st));
+    WW_CHECK(ctx, hipMemcpyAsync(ctx->hsmall, ctx->dsmall, sizeof(double) * 20,
+                                 hipMemcpyDeviceToHost, ctx->st));
+    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
+    *max_abs = ctx->hsmall[1];
+    *l1 = ctx->hsmall[2];
+    return WW_OK;
+}
+
+int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[5])
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !ms) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    if (reps < 1 || reps > 1000) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "reps must be in 1..1000");
+    DevGuard dg(ctx->cfg.device);
+    if (ctx->cfg.precision == WW_FP64) return time_kernels_t<double>(ctx, (double *)d_u, reps, ms);
+    return time_kernels_t<float>(ctx, (float *)d_u, reps, ms);
+}
+
+}  // extern "C"

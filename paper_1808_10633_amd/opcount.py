@@ -1,0 +1,48 @@
+"""Algorithmic FP64 operation count of one interface of the characteristic
+WENO5 sweep, as formulated in ``csrc/ww_sweep.hip``.
+
+Convention: an add, multiply, min/max or compare-select is 1 flop, a fused
+multiply-add is 2, a division or square root is 1 (they take several VALU
+instructions, so a fraction of peak computed with this count understates the
+VALU occupancy).  The count follows the kernel's steps; it is the figure the
+benchmark divides by the measured kernel time.
+"""
+
+# per-step counts for one interface i+1/2
+STEPS = {
+    # six stencil cells: velocities (3), total pressure (7), physical flux (24),
+    # |lambda^s| for seven fields (6) and their running maxima (7)
+    "cell fluxes and LF speeds (6 cells x 47)": 6 * 47,
+    # central combination (-F1 + 7F2 + 7F3 - F4)/12 of 7 components (42) and
+    # the 5 differences of F and U (70)
+    "central term and differences": 42 + 70,
+    # mean state (22), sound/Alfven/fast/slow speeds and Roe-Balsara
+    # normalisation (53), row/column coefficients (30)
+    "interface state and eigen-system": 105,
+    "divisions and square roots of the eigen-system": 5 + 8,
+    # dW/dU applied to 11 vectors (central term, 5 flux and 5 state
+    # differences): 4 x 3 + 14 flops, plus the rotation onto (beta, perp): 12
+    "primitive transform of 11 vectors (11 x 35)": 11 * 35,
+    # projections onto the 7 left eigenvectors: fast and slow pairs
+    # (6 per vector + 22 sign combinations), Alfven (2 per vector + 22),
+    # entropy (2 per vector)
+    "characteristic projections": 88 + 88 + 44 + 22,
+    # per field: LF split of 5 differences on both sides (30), two phi_N
+    # (smoothness 8+18, squares 3, weights 9, interpolant 12 = 50 each),
+    # eq. (1) combination (2)
+    "WENO5 weights and fluxes (7 fields x 132)": 7 * 132,
+    "WENO5 divisions (7 fields x 2)": 14,
+    # back-projection: pair sums/differences and primitive columns (31),
+    # rotation back (12), dU/dW (23)
+    "back-projection": 31 + 12 + 23,
+}
+
+
+def flops_per_interface() -> int:
+    return int(sum(STEPS.values()))
+
+
+if __name__ == "__main__":
+    for k, v in STEPS.items():
+        print(f"{v:6d}  {k}")
+    print(f"{flops_per_interface():6d}  total per interface")

@@ -1,0 +1,198 @@
+"""Thin ctypes binding of the C ABI in ``include/wombat_weno.h``.
+
+Argument marshalling only: every step of the stage runs in the HIP library
+``libwombat_weno.so``.  Device memory and streams come from PyTorch; tensors
+are passed by ``data_ptr()``.  There is no fallback: without the built
+library (or without a GPU) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwombat_weno.so")
+
+WW_OK = 0
+WW_ERR_INVALID_ARG = -1
+WW_ERR_UNSUPPORTED = -2
+WW_ERR_OOM = -3
+WW_ERR_HIP = -4
+WW_ERR_NONPHYSICAL = -5
+WW_ERR_USER_BC = -6
+WW_ERR_STATE = -7
+_NAMES = {0: "WW_OK", -1: "WW_ERR_INVALID_ARG", -2: "WW_ERR_UNSUPPORTED", -3: "WW_ERR_OOM",
+          -4: "WW_ERR_HIP", -5: "WW_ERR_NONPHYSICAL", -6: "WW_ERR_USER_BC", -7: "WW_ERR_STATE"}
+
+WW_FP64 = 0
+WW_FP32_MIXED = 1
+BC_PERIODIC, BC_OUTFLOW, BC_USER = 0, 1, 2
+
+USER_BC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p)
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("ng", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("eps", C.c_double),
+                ("precision", C.c_int), ("bc", C.c_int * 6),
+                ("user_bc", USER_BC_FN), ("user_bc_ctx", C.c_void_p),
+                ("stream", C.c_void_p), ("device", C.c_int)]
+
+
+class WenoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1808_10633_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, d = C.c_void_p, C.c_int, C.c_double
+        L.wombat_weno_abi_version.restype = i32
+        L.wombat_weno_config_default.argtypes = [C.POINTER(Config)]
+        L.wombat_weno_validate_config.argtypes = [C.POINTER(Config)]
+        L.wombat_weno_state_elems.argtypes = [C.POINTER(Config)]
+        L.wombat_weno_state_elems.restype = C.c_int64
+        L.wombat_weno_init.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+        L.wombat_weno_destroy.argtypes = [vp]
+        L.wombat_weno_destroy.restype = None
+        L.wombat_weno_last_error.argtypes = [vp]
+        L.wombat_weno_last_error.restype = C.c_char_p
+        L.wombat_weno_fill_ghosts.argtypes = [vp, vp]
+        L.wombat_weno_cfl_dt.argtypes = [vp, vp, C.POINTER(d)]
+        L.wombat_weno_cfl_dt_device.argtypes = [vp, vp, vp, vp]
+        L.wombat_weno_rhs.argtypes = [vp, vp, vp]
+        L.wombat_weno_stage.argtypes = [vp, i32, d, vp, vp, vp, vp]
+        L.wombat_weno_step.argtypes = [vp, vp, d, C.POINTER(d)]
+        L.wombat_weno_sums.argtypes = [vp, vp, C.POINTER(d)]
+        L.wombat_weno_divb.argtypes = [vp, vp, C.POINTER(d), C.POINTER(d)]
+        L.wombat_weno_time_kernels.argtypes = [vp, vp, i32, C.POINTER(d)]
+        _lib = L
+    return _lib
+
+
+def last_error(ctx=None) -> str:
+    s = lib().wombat_weno_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, cfl=0.4,
+                eps=1e-6, precision=WW_FP64, bc=(0, 0, 0, 0, 0, 0), user_bc=None,
+                stream=None, device=0) -> Config:
+    cfg = Config()
+    lib().wombat_weno_config_default(C.byref(cfg))
+    cfg.nx, cfg.ny, cfg.nz, cfg.ng = nx, ny, nz, 3
+    cfg.dx = 1.0 / nx if dx is None else dx
+    cfg.dy = (1.0 / ny if ny > 1 else 1.0) if dy is None else dy
+    cfg.dz = (1.0 / nz if nz > 1 else 1.0) if dz is None else dz
+    cfg.gamma, cfg.cfl, cfg.eps, cfg.precision = gamma, cfl, eps, precision
+    for i in range(6):
+        cfg.bc[i] = int(bc[i])
+    if user_bc is not None:
+        cfg.user_bc = user_bc
+    cfg.stream = stream
+    cfg.device = device
+    return cfg
+
+
+def _check(code, ctx=None):
+    if code != WW_OK:
+        raise WenoError(code, last_error(ctx))
+
+
+class Context:
+    """One solver context (a ``wombat_weno_t``) for a fixed box.
+
+    ``state`` tensors must be contiguous CUDA tensors of shape
+    (8, nz+2gz, ny+2gy, nx+2gx) and dtype float64 (WW_FP64) or float32
+    (WW_FP32_MIXED), on the context's device.
+    """
+
+    def __init__(self, nx, ny=1, nz=1, **kw):
+        import torch
+        if "stream" not in kw or kw["stream"] is None:
+            kw["stream"] = torch.cuda.current_stream().cuda_stream
+        if "device" not in kw:
+            kw["device"] = torch.cuda.current_device()
+        self.cfg = make_config(nx, ny, nz, **kw)
+        self._user_bc = kw.get("user_bc")
+        h = C.c_void_p()
+        _check(lib().wombat_weno_init(C.byref(self.cfg), C.byref(h)))
+        self.h = h
+        self.dtype = torch.float64 if self.cfg.precision == WW_FP64 else torch.float32
+        g = [3 if n > 1 else 0 for n in (nx, ny, nz)]
+        self.shape = (8, nz + 2 * g[2], ny + 2 * g[1], nx + 2 * g[0])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wombat_weno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptr(self, t, name):
+        if t is None:
+            return None
+        if (not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != self.shape
+                or not t.is_contiguous()):
+            raise ValueError(f"{name}: need contiguous cuda {self.dtype} {self.shape}, got "
+                             f"{t.device} {t.dtype} {tuple(t.shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def new_state(self):
+        import torch
+        return torch.zeros(self.shape, dtype=self.dtype, device=f"cuda:{self.cfg.device}")
+
+    def fill_ghosts(self, u):
+        _check(lib().wombat_weno_fill_ghosts(self.h, self._ptr(u, "u")), self.h)
+
+    def cfl_dt(self, u) -> float:
+        dt = C.c_double()
+        _check(lib().wombat_weno_cfl_dt(self.h, self._ptr(u, "u"), C.byref(dt)), self.h)
+        return dt.value
+
+    def cfl_dt_device(self, u, d_dt, d_flag):
+        _check(lib().wombat_weno_cfl_dt_device(self.h, self._ptr(u, "u"), C.c_void_p(d_dt.data_ptr()),
+                                               C.c_void_p(d_flag.data_ptr())), self.h)
+
+    def rhs(self, u, dudt):
+        _check(lib().wombat_weno_rhs(self.h, self._ptr(u, "u"), self._ptr(dudt, "dudt")), self.h)
+
+    def stage(self, s, dt, u0, us_in, acc, us_out):
+        _check(lib().wombat_weno_stage(self.h, int(s), float(dt), self._ptr(u0, "u0"),
+                                       self._ptr(us_in, "us_in"), self._ptr(acc, "acc"),
+                                       self._ptr(us_out, "us_out")), self.h)
+
+    def step(self, u, dt=0.0) -> float:
+        used = C.c_double()
+        _check(lib().wombat_weno_step(self.h, self._ptr(u, "u"), float(dt), C.byref(used)), self.h)
+        return used.value
+
+    def sums(self, u):
+        out = (C.c_double * 8)()
+        _check(lib().wombat_weno_sums(self.h, self._ptr(u, "u"), out), self.h)
+        return list(out)
+
+    def time_kernels(self, u, reps=10):
+        """Average ms per launch: ghosts, sweep x, y, z, update."""
+        out = (C.c_double * 5)()
+        _check(lib().wombat_weno_time_kernels(self.h, self._ptr(u, "u"), int(reps), out), self.h)
+        return list(out)
+
+    def divb(self, u):
+        mx, l1 = C.c_double(), C.c_double()
+        _check(lib().wombat_weno_divb(self.h, self._ptr(u, "u"), C.byref(mx), C.byref(l1)), self.h)
+        return mx.value, l1.value

@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/wombat_weno.h, and rejects invalid
+configurations before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1808_10633_amd import wombat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(wombat_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(wombat.LIB_PATH):
+        pytest.fail("libwombat_weno.so is not built (run __graft_entry__.build())")
+    return wombat.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 14, names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_abi_version(lib):
+    assert lib.wombat_weno_abi_version() == 1
+
+
+def _cfg(**kw):
+    cfg = wombat.Config()
+    assert wombat.lib().wombat_weno_config_default(C.byref(cfg)) == 0
+    for k, v in kw.items():
+        if k == "bc":
+            for i in range(6):
+                cfg.bc[i] = v[i]
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+def test_default_config_is_valid(lib):
+    cfg = _cfg()
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == 0
+    assert lib.wombat_weno_state_elems(C.byref(cfg)) == 8 * 38 ** 3
+    cfg2 = _cfg(ny=1, dy=1.0)
+    assert lib.wombat_weno_state_elems(C.byref(cfg2)) == 8 * 38 * 1 * 38
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(nx=0), "cell counts"),
+    (dict(ny=2), "at least 3"),
+    (dict(nx=1, ny=1, nz=1), "more than one cell"),
+    (dict(ng=2), "ng must be 3"),
+    (dict(gamma=1.0), "gamma"),
+    (dict(cfl=1.5), "cfl"),
+    (dict(cfl=0.0), "cfl"),
+    (dict(eps=0.0), "eps"),
+    (dict(dx=-1.0), "widths"),
+    (dict(dz=float("nan")), "widths"),
+    (dict(precision=7), "precision"),
+    (dict(bc=(0, 1, 0, 0, 0, 0)), "both faces"),
+    (dict(bc=(2, 2, 0, 0, 0, 0)), "user_bc"),
+    (dict(bc=(5, 5, 0, 0, 0, 0)), "unknown boundary"),
+])
+def test_invalid_configs_rejected(lib, kw, frag):
+    cfg = _cfg(**kw)
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == wombat.WW_ERR_INVALID_ARG
+    assert frag in wombat.last_error()
+    h = C.c_void_p(1234)
+    assert lib.wombat_weno_init(C.byref(cfg), C.byref(h)) == wombat.WW_ERR_INVALID_ARG
+    assert h.value == 1234      # out untouched on failure
+
+
+def test_null_arguments(lib):
+    assert lib.wombat_weno_validate_config(None) == wombat.WW_ERR_INVALID_ARG
+    assert lib.wombat_weno_init(None, None) == wombat.WW_ERR_INVALID_ARG
+    lib.wombat_weno_destroy(None)   # NULL-safe
+    assert lib.wombat_weno_fill_ghosts(None, None) == wombat.WW_ERR_INVALID_ARG
+    d = C.c_double()
+    assert lib.wombat_weno_cfl_dt(None, None, C.byref(d)) == wombat.WW_ERR_INVALID_ARG
+    assert lib.wombat_weno_step(None, None, 0.0, None) == wombat.WW_ERR_INVALID_ARG
+    assert lib.wombat_weno_stage(None, 0, 0.1, None, None, None, None) == wombat.WW_ERR_INVALID_ARG
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    # No silent fallback: a missing library is an error, not a CPU path.
+    monkeypatch.setattr(wombat, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(wombat, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        wombat.lib()
