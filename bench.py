@@ -24,10 +24,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-stage updates/s (WENO5-MHD 512^3) FP64 vs FP32/learned at stated L1 err; %HBM"
 
-# Algorithmic work of one interface of the characteristic sweep (FP64 ops,
-# one fused multiply-add counted as 2 flops), and the FP64 vector peak.
-FLOP_PER_INTERFACE = None   # filled from paper_1808_10633_amd.opcount
-FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+
+# HBM bytes per launch of the timed sweep kernel from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs (scaled by a 1 GiB copy; see profiles/), valid only for
+# the sweep source they were taken on (sha256 of ww_sweep.hip + ww_internal.h).
+MEASURED_TRAFFIC = {
+    ("8adfd3dfffe20d8d", "fp64", 512): {"read": 24.04e9, "write": 7.83e9,
+                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
+}
+
+
+def sweep_source_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1808_10633_amd", "csrc")
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("ww_sweep.hip", "ww_internal.h"))
+    return hashlib.sha256(src).hexdigest()[:16]
 
 
 def parse():
@@ -38,7 +50,22 @@ def parse():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the event timing")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy kernel of known size: reads and writes mib MiB once."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
 def cpu_baseline(n):
@@ -63,6 +90,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU path is a "
               "design (halo-exchanged bricks), not part of this build", file=sys.stderr)
         sys.exit(2)
+    if a.copy_mib:
+        copy_calibration(a.copy_mib)
+        return
     import torch
 
     from paper_1808_10633_amd import inputs, opcount, wombat
@@ -84,13 +114,16 @@ def main():
     zs = n ** 3 * 4 * a.steps / el
 
     # dominant kernel: the characteristic sweeps; HIP events on the library stream
-    ms = ctx.time_kernels(u, reps=5)
+    ms = ctx.time_kernels(u, reps=a.reps)
     nface = [(n + 1) * (n + 2) * (n + 2)] * 3
     fpi = opcount.flops_per_interface()
     sweep_ms = ms[2]      # y sweep (x and z reported beside it)
     achieved = fpi * nface[1] / (sweep_ms * 1e-3) / 1e12
+    tr = MEASURED_TRAFFIC.get((sweep_source_hash(), "fp64", n))
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
+            "traffic_source": tr["profile"] if tr else None,
             "kernel": "sweep_kernel<1,double> (y sweep)",
             "flop_per_interface": fpi, "interfaces_per_launch": nface[1],
             "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
