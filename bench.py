@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "zone-stage updates/s (WENO5-MHD 512^3) FP64 vs FP32/learned at stated L1 err; %HBM"
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 
 # HBM bytes per launch of the timed sweep kernel from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs (scaled by a 1 GiB copy; see profiles/), valid only for
@@ -49,6 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 precision form")
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the event timing")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -66,6 +68,21 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
+
+
+def roofline(ms, n, prec, fpi, peak):
+    """Roofline of the dominant kernel (the y sweep) from event timings."""
+    nface = (n + 1) * (n + 2) * (n + 2)
+    achieved = fpi * nface / (ms[2] * 1e-3) / 1e12
+    tr = MEASURED_TRAFFIC.get((sweep_source_hash(), prec, n))
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
+            "traffic_source": tr["profile"] if tr else None,
+            "kernel": f"sweep_kernel<1,{'double' if prec == 'fp64' else 'float'}> (y sweep)",
+            "flop_per_interface": fpi, "interfaces_per_launch": nface,
+            "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
+                          "update": ms[4]}}
 
 
 def cpu_baseline(n):
@@ -100,14 +117,16 @@ def main():
     torch.cuda.set_device(0)
     n = a.n
     u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")
+    u_ic = u.clone()
     ctx = wombat.Context(n, n, n, precision=wombat.WW_FP64, cfl=0.4)
     print(f"[bench] {n}^3 FP64 turbulence ready; warmup {a.warmup}", file=sys.stderr, flush=True)
+    dts = []
     for _ in range(a.warmup):
-        ctx.step(u, 0.0)
+        dts.append(ctx.step(u, 0.0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        ctx.step(u, 0.0)
+        dts.append(ctx.step(u, 0.0))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     print(f"[bench] {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
@@ -115,19 +134,7 @@ def main():
 
     # dominant kernel: the characteristic sweeps; HIP events on the library stream
     ms = ctx.time_kernels(u, reps=a.reps)
-    nface = [(n + 1) * (n + 2) * (n + 2)] * 3
-    fpi = opcount.flops_per_interface()
-    sweep_ms = ms[2]      # y sweep (x and z reported beside it)
-    achieved = fpi * nface[1] / (sweep_ms * 1e-3) / 1e12
-    tr = MEASURED_TRAFFIC.get((sweep_source_hash(), "fp64", n))
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
-            "traffic_source": tr["profile"] if tr else None,
-            "kernel": "sweep_kernel<1,double> (y sweep)",
-            "flop_per_interface": fpi, "interfaces_per_launch": nface[1],
-            "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
-                          "update": ms[4]}}
+    roof = roofline(ms, n, "fp64", opcount.flops_per_interface(), FP64_VECTOR_PEAK_TFLOPS)
     out = {"metric": METRIC, "value": zs, "unit": "zone-stage updates/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": el / a.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -136,7 +143,43 @@ def main():
                                   "gamma 5/3, FP64 characteristic WENO5 + CT + RK4, CFL 0.4 step",
                       "n": n, "precision": "fp64"},
            "roofline": roof}
-    del ctx, u
+    del ctx
+    torch.cuda.empty_cache()
+
+    if not a.no_fp32:
+        # precision form: FP32 state/fluxes/weights, FP64 islands; same initial
+        # state, the FP64 run's step sizes replayed (its own CFL reduction
+        # still runs every step), final states compared
+        u32 = u_ic.float().contiguous()
+        c32 = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4)
+        for i in range(a.warmup):
+            c32.cfl_dt(u32)
+            c32.step(u32, dts[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(a.steps):
+            c32.cfl_dt(u32)
+            c32.step(u32, dts[a.warmup + i])
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t0
+        sl = inputs.interior_slices(n, n, n)
+        l1, linf = [], []
+        for v in range(8):
+            d = (u32[sl][v].double() - u[sl][v]).abs()
+            ref = u[sl][v].abs()
+            if float(ref.max()) > 0:
+                l1.append(float(d.mean() / ref.mean()))
+                linf.append(float(d.max() / ref.max()))
+        ms32 = c32.time_kernels(u32, reps=a.reps)
+        out["forms"] = {"fp32_mixed": {
+            "value": n ** 3 * 4 * a.steps / el32, "ms_per_step": el32 / a.steps * 1e3,
+            "speedup_vs_fp64": (n ** 3 * 4 * a.steps / el32) / zs, "dtype": "f32 (f64 islands)",
+            "l1_rel_vs_fp64_max_var": max(l1), "linf_rel_vs_fp64_max_var": max(linf),
+            "compared_after_steps": a.warmup + a.steps,
+            "roofline": roofline(ms32, n, "fp32", opcount.flops_per_interface(), FP32_VECTOR_PEAK_TFLOPS)}}
+        del c32, u32
+        torch.cuda.empty_cache()
+    del u, u_ic
     torch.cuda.empty_cache()
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -203,7 +203,7 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
 {
     int rc = fill_ghosts_t<T>(c, us);
     if (rc) return rc;
-    ww::Phys P{ c->cfg.gamma, c->cfg.eps };
+    ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
     for (int d = 0; d < 3; ++d) {
         if (!c->G.act[d]) continue;
         WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->st));
@@ -227,7 +227,7 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
 {
     int rc = fill_ghosts_t<T>(c, u);
     if (rc) return rc;
-    ww::Phys P{ c->cfg.gamma, c->cfg.eps };
+    ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
     ww::StageCoef k{ 0, 0, 0.0, 0.0 };
     for (int which = 0; which < 5; ++which) {
         ms[which] = 0.0;

@@ -33,6 +33,7 @@ constexpr int NFC = 7;   // stored face-flux components
 
 struct Phys {
     double gamma, eps;
+    double igm1;       // 1 / (gamma - 1)
 };
 
 // Launchers (return the hipError_t of the launch).

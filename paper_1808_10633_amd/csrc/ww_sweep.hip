@@ -10,8 +10,9 @@
 // Per interface:
 //   1. the six stencil cells i-2..i+3 are read from LDS; their physical
 //      fluxes are formed; the central combination (-F_{i-1} + 7F_i + 7F_{i+1}
-//      - F_{i+2})/12 and the five cell-to-cell differences of F and U are
-//      taken (eq. 1 is linear in these), and the largest |lambda^s| per field
+//      - F_{i+2})/12 (kept doubled) and the five cell-to-cell differences of F
+//      and U are taken (eq. 1 is linear in these; the projection rows carry the
+//      1/2 of the Lax-Friedrichs split, a power-of-two scaling), and the largest |lambda^s| per field
 //      over the stencil gives the local Lax-Friedrichs speed;
 //   2. the mean state of cells i and i+1 (arithmetic mean of the primitive
 //      variables) gives the seven-wave eigen-system with the Roe-Balsara
@@ -39,35 +40,58 @@ constexpr int TILE = 64;    // lanes per row
 constexpr int ROWS = 4;     // waves per block
 constexpr int NCX = TILE + 5;
 
-template <typename T>
-__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T eps)
+// Reciprocal: hardware estimate refined by Newton steps (two in FP64, one in
+// FP32), to within rounding of the correctly rounded quotient.
+__device__ __forceinline__ double frcp(double x)
 {
-    // smoothness indicators, eqs. (5)-(7)
-    T ab = a - b, a3b = a - T(3) * b;
-    T bc = b - c, bpc = b + c;
-    T cd = c - d, c3d = T(3) * c - d;
-    T q0 = eps + (T(13) * ab * ab + T(3) * a3b * a3b);
-    T q1 = eps + (T(13) * bc * bc + T(3) * bpc * bpc);
-    T q2 = eps + (T(13) * cd * cd + T(3) * c3d * c3d);
-    q0 *= q0; q1 *= q1; q2 *= q2;
-    // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
-    // written over the common denominator q0 q1 q2 (one division).
-    T n0 = q1 * q2, n1 = T(6) * q0 * q2, n2 = T(3) * q0 * q1;
-    T inv = T(1) / (n0 + n1 + n2);
-    T w0 = n0 * inv, w2 = n2 * inv;
-    return w0 * (a - T(2) * b + c) * T(1.0 / 3.0) + (w2 - T(0.5)) * (b - T(2) * c + d) * T(1.0 / 6.0);
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
 }
 
-// eq. (1) for one field from its projected central term, flux and state
-// differences (k = 0..4 at i-3/2 .. i+5/2) and LF speed al.
+// phi_N of eq. (2) with the weights of eqs. (3)-(7).  e4 = epsilon / 4.
+template <typename T>
+__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4)
+{
+    // Smoothness indicators of eqs. (5)-(7), expanded into the quadratic forms
+    // IS_0 = 16a^2 - 44ab + 40b^2, IS_1 = 16b^2 - 20bc + 16c^2,
+    // IS_2 = 40c^2 - 44cd + 16d^2 (all positive definite), and divided by 4
+    // together with epsilon: the weights depend only on ratios of the
+    // (epsilon + IS_k), so they are unchanged (an exact power-of-two scale).
+    T b2 = b * b, c2 = c * c;
+    T q0 = fma(a, fma(T(4), a, T(-11) * b), fma(T(10), b2, e4));
+    T q1 = fma(T(4), b2 + c2, fma(T(-5), b * c, e4));
+    T q2 = fma(d, fma(T(4), d, T(-11) * c), fma(T(10), c2, e4));
+    q0 *= q0; q1 *= q1; q2 *= q2;
+    // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
+    // written over the common denominator q0 q1 q2 (one reciprocal).
+    T n0 = q1 * q2, n1 = T(6) * q0 * q2, n2 = T(3) * q0 * q1;
+    T inv = frcp(n0 + n1 + n2);
+    // eq. (2): omega_0 (a-2b+c)/3 + (omega_2 - 1/2)(b-2c+d)/6
+    T x3 = (a - T(2) * b + c) * T(1.0 / 3.0);
+    T y6 = (b - T(2) * c + d) * T(1.0 / 6.0);
+    return fma(inv, fma(n0, x3, n2 * y6), T(-0.5) * y6);
+}
+
+// eq. (1) for one field.  cc: projected central term; df, du: projected flux
+// and state differences (k = 0..4 at i-3/2 .. i+5/2), both already carrying
+// the 1/2 of the Lax-Friedrichs split; al: LF speed.
 template <typename T>
 __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps)
 {
     T dp[5], dm[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        dp[k] = T(0.5) * (df[k] + al * du[k]);
-        dm[k] = T(0.5) * (df[k] - al * du[k]);
+        dp[k] = fma(al, du[k], df[k]);
+        dm[k] = fma(-al, du[k], df[k]);
     }
     return cc - phi_n(dp[0], dp[1], dp[2], dp[3], eps) + phi_n(dm[4], dm[3], dm[2], dm[1], eps);
 }
@@ -81,18 +105,18 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
       m2 = u[id + cm[3] * sv], bn = u[id + cm[4] * sv], b1 = u[id + cm[5] * sv],
       b2 = u[id + cm[6] * sv], e = u[id + cm[7] * sv];
     // pressure recovery (kept in FP64 for every storage type)
-    double rd = r;
-    double pd = (gamma - 1.0) * ((double)e - 0.5 * ((double)mn * mn + (double)m1 * m1 + (double)m2 * m2) / rd
+    double ird = frcp((double)r);
+    double pd = (gamma - 1.0) * ((double)e - 0.5 * ((double)mn * mn + (double)m1 * m1 + (double)m2 * m2) * ird
                                  - 0.5 * ((double)bn * bn + (double)b1 * b1 + (double)b2 * b2));
     T p = (T)pd;
-    T ir = T(1) / r;
+    T ir = (T)ird;
     T a2 = T(gamma) * p * ir;
     T bn2 = bn * bn * ir;
     T bt2 = (b1 * b1 + b2 * b2) * ir;
     T dd = a2 - bn2;
     T disc = dd * dd + bt2 * (T(2) * a2 + T(2) * bn2 + bt2);
     T cf2 = T(0.5) * (a2 + bn2 + bt2 + sqrt(disc));
-    T cs2 = a2 * bn2 / cf2;
+    T cs2 = a2 * bn2 * frcp(cf2);
     q[0 * qs] = r;  q[1 * qs] = mn; q[2 * qs] = m1; q[3 * qs] = m2;
     q[4 * qs] = bn; q[5 * qs] = b1; q[6 * qs] = b2; q[7 * qs] = e;
     q[8 * qs] = p;
@@ -107,7 +131,7 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // out: sweep-frame flux (rho, mn, mt1, mt2, Bt1, Bt2, E).
 template <typename T>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
-                                          double gamma, T eps, T (&out)[7])
+                                          double gamma, double igm1, T eps, T (&out)[7])
 {
 #define QQ(q, j) sq[(q) * qs + off + (j) * cstr]
     T C[7], dY[5][7], dZ[5][7], am[7];
@@ -130,7 +154,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
             am[c] = (j == 0) ? lam[c] : fmax(am[c], lam[c]);
             if (j == 1) C[c] = -Fj[c];
             if (j == 2 || j == 3) C[c] += T(7) * Fj[c];
-            if (j == 4) C[c] = (C[c] - Fj[c]) * T(1.0 / 12.0);
+            if (j == 4) C[c] = (C[c] - Fj[c]) * T(1.0 / 6.0);   // twice the central term
             if (j > 0) { dY[j - 1][c] = Fj[c] - Fp[c]; dZ[j - 1][c] = Uj[c] - Up[c]; }
             Fp[c] = Fj[c];
             Up[c] = Uj[c];
@@ -149,45 +173,49 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     double b2b = 0.5 * ((double)QQ(6, 2) + (double)QQ(6, 3));
     double pb = 0.5 * ((double)QQ(8, 2) + (double)QQ(8, 3));
 #undef QQ
-    double irb = 1.0 / rb;
+    double irb = frcp(rb);
     double a2 = gamma * pb * irb;
     double bn2 = bnb * bnb * irb;
     double bt2 = (b1b * b1b + b2b * b2b) * irb;
     double dd = a2 - bn2;
     double sqD = sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2));
     double cf2 = 0.5 * (a2 + bn2 + bt2 + sqD);
-    double cs2 = a2 * bn2 / cf2;
+    double icf2 = frcp(cf2);
+    double cs2 = a2 * bn2 * icf2;
     double af, as;
     if (sqD <= 1e-12 * (a2 + bn2 + bt2)) {
         af = 1.0; as = 0.0;
     } else {
         // (cf^2 - a^2)(cf^2 - bn^2) = bt^2 cf^2 avoids the cancellation
         double P, Q;
-        if (dd >= 0.0) { P = 0.5 * (dd + bt2 + sqD); Q = bt2 * cf2 / P; }
-        else           { Q = 0.5 * (-dd + bt2 + sqD); P = bt2 * cf2 / Q; }
-        double af2 = fmin(fmax(a2 * P / (cf2 * sqD), 0.0), 1.0);
-        double as2 = fmin(fmax(Q / sqD, 0.0), 1.0);
+        if (dd >= 0.0) { P = 0.5 * (dd + bt2 + sqD); Q = bt2 * cf2 * frcp(P); }
+        else           { Q = 0.5 * (-dd + bt2 + sqD); P = bt2 * cf2 * frcp(Q); }
+        double isq = frcp(sqD);
+        double af2 = fmin(fmax(a2 * P * icf2 * isq, 0.0), 1.0);
+        double as2 = fmin(fmax(Q * isq, 0.0), 1.0);
         af = sqrt(af2); as = sqrt(as2);
     }
     double be1, be2;
     if (bt2 > 1e-24 * (a2 + bn2)) {
-        double ibt = 1.0 / sqrt(b1b * b1b + b2b * b2b);
+        double ibt = frcp(sqrt(b1b * b1b + b2b * b2b));
         be1 = b1b * ibt; be2 = b2b * ibt;
     } else {
         be1 = be2 = 0.70710678118654752440;
     }
     double sg = (bnb >= 0.0) ? 1.0 : -1.0;
     double cfm = sqrt(cf2), csm = sqrt(cs2), am_ = sqrt(a2), sr = sqrt(rb);
+    double isr = frcp(sr), ia2 = frcp(a2);
     double gm1 = gamma - 1.0;
     double hv2 = 0.5 * (vnb * vnb + v1b * v1b + v2b * v2b);
 
-    // rows of L_W (scaled), per wave pair: odd (sign-flipping) and even parts
-    const T i2a2 = T(0.5 / a2);
+    // rows of L_W, per wave pair: odd (sign-flipping) and even parts, with
+    // the 1/2 of the Lax-Friedrichs split folded in (exact power-of-two scale)
+    const T i2a2 = T(0.25 * ia2);
     const T kf1 = T(af * cfm) * i2a2, kf2 = T(as * csm * sg) * i2a2;
-    const T kf4 = T(as * am_ / sr) * i2a2, kf6 = T(af * irb) * i2a2;
+    const T kf4 = T(as * am_ * isr) * i2a2, kf6 = T(af * irb) * i2a2;
     const T ks1 = T(as * csm) * i2a2, ks2 = T(af * cfm * sg) * i2a2;
-    const T ks4 = T(af * am_ / sr) * i2a2, ks6 = T(as * irb) * i2a2;
-    const T ka3 = T(0.5 * sg), ka5 = T(0.5 / sr), ke6 = T(1.0 / a2);
+    const T ks4 = T(af * am_ * isr) * i2a2, ks6 = T(as * irb) * i2a2;
+    const T ka3 = T(0.25 * sg), ka5 = T(0.25 * isr), ke6 = T(ia2), kh = T(0.5);
 
     // dW/dU at the interface state followed by the rotation of the
     // transverse components onto (beta, perpendicular).
@@ -207,7 +235,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     for (int k = 0; k < 5; ++k) { xf(dY[k]); xf(dZ[k]); }
 
     T G[7] = { T(0), T(0), T(0), T(0), T(0), T(0), T(0) };
-    const T teps = eps;
+    const T teps = T(0.25) * eps;     // epsilon / 4 for phi_n
 
     // One wave pair (sigma = -1 field index lo, sigma = +1 field index hi).
     // proj(X, odd, even) gives the odd and even parts of the row applied to X.
@@ -250,11 +278,11 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     G[5] += T(sr) * S;
     // entropy (field 3)
     {
-        T cc = C[0] - ke6 * C[6], df[5], du[5];
+        T cc = kh * (C[0] - ke6 * C[6]), df[5], du[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            df[k] = dY[k][0] - ke6 * dY[k][6];
-            du[k] = dZ[k][0] - ke6 * dZ[k][6];
+            df[k] = kh * (dY[k][0] - ke6 * dY[k][6]);
+            du[k] = kh * (dZ[k][0] - ke6 * dZ[k][6]);
         }
         G[0] += weno_field(cc, df, du, am[3], teps);
     }
@@ -270,7 +298,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     out[4] = gb1;
     out[5] = gb2;
     out[6] = th * G[0] + trb * (tv * G[1] + t1 * gv1 + t2 * gv2) + tb1 * gb1 + tb2 * gb2
-           + G[6] * T(1.0 / gm1);
+           + G[6] * T(igm1);
 }
 
 template <int DIR, typename T>
@@ -332,7 +360,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T *__restrict__ u, T *
     __syncthreads();
     if (!active) return;
     T out[7];
-    face_flux<T>(sq, NC, off, cstr, P.gamma, (T)P.eps, out);
+    face_flux<T>(sq, NC, off, cstr, P.gamma, P.igm1, (T)P.eps, out);
     const long fi = F.idx(pos[0], pos[1], pos[2]);
     // grid-frame components: rho, mx, my, mz, B_(N+1), B_(N+2), E
     flux[0 * F.sc + fi] = out[0];

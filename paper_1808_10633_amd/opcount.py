@@ -27,10 +27,11 @@ STEPS = {
     # (6 per vector + 22 sign combinations), Alfven (2 per vector + 22),
     # entropy (2 per vector)
     "characteristic projections": 88 + 88 + 44 + 22,
-    # per field: LF split of 5 differences on both sides (30), two phi_N
-    # (smoothness 8+18, squares 3, weights 9, interpolant 12 = 50 each),
-    # eq. (1) combination (2)
-    "WENO5 weights and fluxes (7 fields x 132)": 7 * 132,
+    # per field: LF split of 5 differences on both sides as fused
+    # multiply-adds (20), two phi_N (smoothness indicators as expanded
+    # quadratic forms 22, squares 3, weights over one denominator 9,
+    # interpolant 12 = 46 each), eq. (1) combination (2)
+    "WENO5 weights and fluxes (7 fields x 114)": 7 * 114,
     "WENO5 divisions (7 fields x 2)": 14,
     # back-projection: pair sums/differences and primitive columns (31),
     # rotation back (12), dU/dW (23)
