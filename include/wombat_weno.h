@@ -186,6 +186,72 @@ int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1)
  * Synchronous. */
 int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[5]);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent periodic patches (Sec. 2.2: the domain is
+ * cut into patches with their own ghost zones that are computed
+ * independently), advanced together by one persistent launch per RK stage.
+ *
+ * ARENA LAYOUT: one caller-owned device array holds every patch's padded
+ * state u[v][k][j][i] (each axis n+6 long, all axes active) starting at the
+ * element offset wombat_weno_batch_patch_offset(b, p); total length
+ * wombat_weno_batch_arena_elems(b) elements of the configured precision.
+ * Every patch is periodic on all faces and has its own CFL time step,
+ * computed on the device in stage 0 of every step and kept there.
+ * ------------------------------------------------------------------------ */
+typedef struct wombat_weno_batch wombat_weno_batch_t;
+
+/* Create a batch of npatch patches; dims (host) holds npatch x (nx, ny, nz),
+ * each edge 8..1024 cells.  From cfg only dx (the cell width of every
+ * patch and axis), gamma, cfl, eps, precision, stream and device are used.
+ * Allocates three work arenas, the face-flux scratch of up to 4 blocks per
+ * CU, the patch table and the schedule (largest patch first onto the
+ * least-loaded block).  *out is written only on success.
+ * Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP, WW_ERR_UNSUPPORTED. */
+int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int32_t *dims,
+                           wombat_weno_batch_t **out);
+
+/* Release a batch (NULL allowed). */
+void wombat_weno_batch_destroy(wombat_weno_batch_t *b);
+
+/* Message of the last failure on b (NULL: of the last failed batch init). */
+const char *wombat_weno_batch_last_error(const wombat_weno_batch_t *b);
+
+/* Elements of one arena; element offset of patch p's padded state (-1 on a
+ * bad argument). */
+int64_t wombat_weno_batch_arena_elems(const wombat_weno_batch_t *b);
+int64_t wombat_weno_batch_patch_offset(const wombat_weno_batch_t *b, int p);
+
+/* One classical RK4 step of every patch of d_arena in place, each with its
+ * own CFL time step: four launches of the persistent stage kernel on the
+ * configured stream.  Asynchronous; the arena's ghosts are overwritten. */
+int wombat_weno_batch_step(wombat_weno_batch_t *b, void *d_arena);
+
+/* As nsteps calls of wombat_weno_batch_step, replaying a HIP graph of one
+ * step (captured on first use for this arena pointer, recaptured when the
+ * pointer or the launch shape changes).  Asynchronous. */
+int wombat_weno_batch_graph_steps(wombat_weno_batch_t *b, void *d_arena, int nsteps);
+
+/* Per-patch time step of the last step and count of non-physical cells
+ * (0 = healthy; a patch with a non-physical cell gets dt = 0 and is left
+ * unadvanced by the step).  Host arrays
+ * of npatch entries, either may be NULL.  Synchronous. */
+int wombat_weno_batch_dt(wombat_weno_batch_t *b, double *h_dt, int32_t *h_flag);
+
+/* Launch shape in use: faces per y/z sweep tile (4 or 8), blocks per CU,
+ * total persistent blocks. */
+int wombat_weno_batch_shape(const wombat_weno_batch_t *b, int *ft, int *blocks_per_cu,
+                            int *nblocks);
+
+/* Autotuner: if cache_path (a text file, one JSON object per line; may be
+ * NULL) holds an entry for this patch set, precision and architecture, use
+ * it; otherwise time one step of every launch shape (faces per tile 4 or 8 x
+ * 1..4 blocks per CU within the occupancy limit) on a private copy of
+ * d_arena (not modified), keep the fastest, append it to cache_path, and
+ * return its time in *best_ms (-1 when taken from the cache).  The copy is
+ * this set-up call's only device allocation.  Synchronous. */
+int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, const char *cache_path,
+                               double *best_ms);
+
 #ifdef __cplusplus
 }
 #endif

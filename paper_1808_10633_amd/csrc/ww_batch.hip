@@ -1,0 +1,208 @@
+// ww_batch.hip -- many independent periodic patches advanced by one
+// persistent launch per RK stage.
+//
+// The patches (arXiv:1808.10633, Sec. 2.2: the domain is cut into patches of
+// 18^3-32^3 zones with ghost zones, each computed independently once its
+// boundary zones are present) live in one arena.  A static schedule assigns
+// whole patches to resident blocks, largest first onto the least-loaded slot,
+// so no block waits on another and no atomics are needed.  A block takes
+// each of its patches through the full stage: (stage 0 only) the patch's CFL
+// time step (0, and the patch left unadvanced, if any cell is non-physical),
+// periodic ghost fill, x/y/z characteristic WENO sweeps into the
+// block's own face-flux scratch, then flux differences, CT and the RK update
+// -- the same device functions as the single-box kernels.
+#include "ww_batch.h"
+#include "ww_sweep_dev.h"
+#include "ww_update_dev.h"
+
+namespace ww {
+namespace {
+
+constexpr int RB = 256;
+
+template <typename T>
+__device__ __forceinline__ void ghost_fill_patch(T *__restrict__ u, const Geom &G)
+{
+    const int tid = threadIdx.x + sw::TILE * threadIdx.y;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int g = G.g[ax], n = G.n[ax];
+        int lo[3], cnt[3];
+        for (int e = 0; e < 3; ++e) {
+            if (e == ax) { lo[e] = 0; cnt[e] = 2 * g; }
+            else if (e < ax) { lo[e] = -G.g[e]; cnt[e] = G.n[e] + 2 * G.g[e]; }
+            else { lo[e] = 0; cnt[e] = G.n[e]; }
+        }
+        const long total = (long)cnt[0] * cnt[1] * cnt[2];
+        for (long t = tid; t < total; t += RB) {
+            int pos[3];
+            pos[0] = (int)(t % cnt[0]) + lo[0];
+            pos[1] = (int)((t / cnt[0]) % cnt[1]) + lo[1];
+            pos[2] = (int)(t / ((long)cnt[0] * cnt[1])) + lo[2];
+            const int gi = pos[ax];
+            const bool low = gi < g;
+            const int x = low ? gi - g : n + (gi - g);
+            int dst[3] = { pos[0], pos[1], pos[2] }, src[3] = { pos[0], pos[1], pos[2] };
+            dst[ax] = x;
+            src[ax] = low ? x + n : x - n;          // periodic
+            const long di = G.base + dst[0] * G.s[0] + dst[1] * G.s[1] + (long)dst[2] * G.s[2];
+            const long si = G.base + src[0] * G.s[0] + src[1] * G.s[1] + (long)src[2] * G.s[2];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[di + v * G.sv] = u[si + v * G.sv];
+        }
+        __syncthreads();
+    }
+}
+
+// CFL time step of one patch (FP64 reduction in fixed order) and its count
+// of non-physical cells.
+template <typename T>
+__device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G, double gamma,
+                                         double cfl, double *dt_out, int32_t *flag_out)
+{
+    __shared__ double smx[RB];
+    __shared__ int sfl[RB];
+    const int tid = threadIdx.x + sw::TILE * threadIdx.y;
+    const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+    double mx = 0.0;
+    int bad = 0;
+    for (long c = tid; c < ncell; c += RB) {
+        int p[3];
+        p[0] = (int)(c % G.n[0]);
+        p[1] = (int)((c / G.n[0]) % G.n[1]);
+        p[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+        const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
+        double q[8];
+        bool fin = true;
+        for (int v = 0; v < 8; ++v) { q[v] = (double)u[id + v * G.sv]; fin = fin && isfinite(q[v]); }
+        double r = q[0], ir = 1.0 / r;
+        double vx = q[1] * ir, vy = q[2] * ir, vz = q[3] * ir;
+        double b2 = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+        double pr = (gamma - 1.0) * (q[7] - 0.5 * (q[1] * vx + q[2] * vy + q[3] * vz) - 0.5 * b2);
+        if (!fin || !(r > 0.0) || !(pr > 0.0)) { ++bad; continue; }
+        double a2 = gamma * pr * ir;
+        double v[3] = { vx, vy, vz };
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double bn2 = q[4 + d] * q[4 + d] * ir;
+            double bt2 = b2 * ir - bn2;
+            bt2 = bt2 < 0.0 ? 0.0 : bt2;
+            double dd = a2 - bn2;
+            double cf2 = 0.5 * (a2 + bn2 + bt2 + sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2)));
+            s += (fabs(v[d]) + sqrt(cf2)) * G.idl[d];
+        }
+        mx = fmax(mx, s);
+    }
+    smx[tid] = mx;
+    sfl[tid] = bad;
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if (tid < h) { smx[tid] = fmax(smx[tid], smx[tid + h]); sfl[tid] += sfl[tid + h]; }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const bool ok = smx[0] > 0.0 && sfl[0] == 0;
+        *dt_out = ok ? cfl / smx[0] : 0.0;
+        *flag_out = sfl[0] > 0 ? sfl[0] : (ok ? 0 : 1);
+    }
+    __syncthreads();
+}
+
+template <int FT, typename T>
+__global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
+{
+    constexpr int C0 = sw::tile_cells<0, FT>(), C1 = sw::tile_cells<1, FT>();
+    constexpr int CMAX = (C0 > C1 ? C0 : C1) > sw::XF_MAXC ? (C0 > C1 ? C0 : C1) : sw::XF_MAXC;
+    __shared__ T sq[sw::NQ * CMAX];
+    __shared__ double sdt;
+    const int b = blockIdx.x;
+    T *ff = a.scratch + (long)b * a.slot_elems;
+    const Phys P = a.P;
+    for (int q = a.sched_ptr[b]; q < a.sched_ptr[b + 1]; ++q) {
+        const int p = a.sched_list[q];
+        const PatchDesc &D = a.pd[p];
+        const Geom G = D.G;
+        T *us = a.us + D.soff;
+        if (a.s == 0) patch_dt<T>(a.u0 + D.soff, G, P.gamma, a.cfl, &a.dt[p], &a.flag[p]);
+        if (threadIdx.x == 0 && threadIdx.y == 0) sdt = a.dt[p];
+        __syncthreads();
+        const double dtp = sdt;
+        __syncthreads();
+        if (dtp == 0.0) continue;        // non-physical patch: left unadvanced
+        ghost_fill_patch<T>(us, G);
+        T *fx = ff, *fy = ff + NFC * D.F[0].sc, *fz = fy + NFC * D.F[1].sc;
+        // x sweep
+        if (D.xflat) {
+            const long nt = ((long)D.F[0].cnt[0] * D.F[0].cnt[1] * D.F[0].cnt[2] + sw::XF_FACES - 1)
+                            / sw::XF_FACES;
+            for (long t = 0; t < nt; ++t) sw::sweep_tile_xflat<T>(us, fx, G, D.F[0], P, t, sq);
+        } else {
+            long na, nb;
+            sw::sweep_tiles<0, FT>(D.F[0], na, nb);
+            for (long tb = 0; tb < nb; ++tb)
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T>(us, fx, G, D.F[0], P, ta, tb, sq);
+        }
+        {
+            long na, nb;
+            sw::sweep_tiles<1, FT>(D.F[1], na, nb);
+            for (long tb = 0; tb < nb; ++tb)
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<1, FT, T>(us, fy, G, D.F[1], P, ta, tb, sq);
+            sw::sweep_tiles<2, FT>(D.F[2], na, nb);
+            for (long tb = 0; tb < nb; ++tb)
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T>(us, fz, G, D.F[2], P, ta, tb, sq);
+        }
+        // flux differences, CT, RK with the patch's own dt
+        up::UpdArgs<T> ua;
+        ua.u0 = a.u0 + D.soff;
+        ua.acc_in = a.acc + D.soff;
+        ua.acc_out = a.acc + D.soff;
+        ua.out = a.out + D.soff;
+        ua.ff[0] = fx; ua.ff[1] = fy; ua.ff[2] = fz;
+        ua.fb[0] = D.F[0]; ua.fb[1] = D.F[1]; ua.fb[2] = D.F[2];
+        ua.G = G;
+        ua.c.mode = 1;
+        ua.c.s = a.s;
+        ua.c.bdt = a.bw * dtp;
+        ua.c.cdt = a.cw * dtp;
+        const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+        const int tid = threadIdx.x + sw::TILE * threadIdx.y;
+        for (long c = tid; c < ncell; c += RB) {
+            int pos[3];
+            pos[0] = (int)(c % G.n[0]);
+            pos[1] = (int)((c / G.n[0]) % G.n[1]);
+            pos[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+            up::update_cell(ua, pos);
+        }
+        __syncthreads();     // the scratch is reused by the next patch
+    }
+}
+
+template <int FT, typename T>
+hipError_t launch_ft(const BatchArgs<T> &a, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_stage_kernel<FT, T>), dim3(nblocks), dim3(sw::TILE, sw::ROWS), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool batch_xflat_ok(int nx, long nrows) { return nx >= 8 && sw::xflat_cells(nx, nrows) <= sw::XF_MAXC; }
+
+template <typename T>
+hipError_t launch_batch_stage(const BatchArgs<T> &a, int ft, int nblocks, hipStream_t st)
+{
+    return ft == 8 ? launch_ft<8, T>(a, nblocks, st) : launch_ft<4, T>(a, nblocks, st);
+}
+
+template <typename T>
+hipError_t batch_occupancy(int ft, int *blocks_per_cu)
+{
+    return ft == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<8, T>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<4, T>, 256, 0);
+}
+
+template hipError_t launch_batch_stage<double>(const BatchArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_batch_stage<float>(const BatchArgs<float> &, int, int, hipStream_t);
+template hipError_t batch_occupancy<double>(int, int *);
+template hipError_t batch_occupancy<float>(int, int *);
+
+}  // namespace ww

@@ -1,0 +1,466 @@
+// ww_sweep_dev.h -- device code of the characteristic WENO5 sweep, shared by
+// the single-box kernels and the batched persistent kernel.
+//
+// One thread computes the flux at one interface i+1/2 of the sweep axis
+// (arXiv:1808.10633, Sec. 2.1, eq. 1 per characteristic field).  A block
+// first stages the cells of its tile (plus the 3-cell halo on each side of
+// the sweep axis) in LDS together with the per-cell quantities every
+// interface needs (pressure, 1/rho, fast/slow/Alfven speeds), so each cell's
+// equation of state and wave speeds are evaluated once per block.
+//
+// Per interface:
+//   1. the six stencil cells i-2..i+3 are read from LDS; their physical
+//      fluxes are formed; the central combination (-F_{i-1} + 7F_i + 7F_{i+1}
+//      - F_{i+2})/12 (kept doubled) and the five cell-to-cell differences of F
+//      and U are taken (eq. 1 is linear in these; the projection rows carry the
+//      1/2 of the Lax-Friedrichs split, a power-of-two scaling), and the
+//      largest |lambda^s| per field over the stencil gives the local
+//      Lax-Friedrichs speed;
+//   2. the mean state of cells i and i+1 (arithmetic mean of the primitive
+//      variables) gives the seven-wave eigen-system with the Roe-Balsara
+//      normalisation; the left eigenvectors are applied as
+//      L_U X = L_W (dW/dU) X: the Jacobian dW/dU once per vector, then the
+//      sparse primitive rows, after rotating the transverse components onto
+//      the (B_t, perpendicular) basis, in which every row has at most four
+//      entries and the +- members of a wave pair share their terms;
+//   3. per field: split F^{s+-} differences, WENO5 weights (eqs. 3-7, with the
+//      three weights put over one common denominator), phi_N (eq. 2), eq. (1);
+//   4. back-projection R_U F^s = (dU/dW) R_W F^s, again through the sparse
+//      primitive columns; the flux is stored in grid components.
+// The sweep axis is a template parameter: no data is transposed.
+#pragma once
+#include "ww_internal.h"
+
+#include <math.h>
+
+namespace ww {
+namespace sw {
+
+constexpr int NQ = 13;      // staged quantities per cell
+// LDS slots: 0 rho, 1 mn, 2 mt1, 3 mt2, 4 Bn, 5 Bt1, 6 Bt2, 7 E,
+//            8 p, 9 1/rho, 10 c_f, 11 c_s, 12 c_A   (sweep frame)
+constexpr int TILE = 64;    // lanes per row
+constexpr int ROWS = 4;     // waves per block
+constexpr int NCX = TILE + 5;
+
+// Reciprocal: hardware estimate refined by Newton steps (two in FP64, one in
+// FP32), to within rounding of the correctly rounded quotient.
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
+// phi_N of eq. (2) with the weights of eqs. (3)-(7).  e4 = epsilon / 4.
+template <typename T>
+__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4)
+{
+    // Smoothness indicators of eqs. (5)-(7), expanded into the quadratic forms
+    // IS_0 = 16a^2 - 44ab + 40b^2, IS_1 = 16b^2 - 20bc + 16c^2,
+    // IS_2 = 40c^2 - 44cd + 16d^2 (all positive definite), and divided by 4
+    // together with epsilon: the weights depend only on ratios of the
+    // (epsilon + IS_k), so they are unchanged (an exact power-of-two scale).
+    T b2 = b * b, c2 = c * c;
+    T q0 = fma(a, fma(T(4), a, T(-11) * b), fma(T(10), b2, e4));
+    T q1 = fma(T(4), b2 + c2, fma(T(-5), b * c, e4));
+    T q2 = fma(d, fma(T(4), d, T(-11) * c), fma(T(10), c2, e4));
+    q0 *= q0; q1 *= q1; q2 *= q2;
+    // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
+    // written over the common denominator q0 q1 q2 (one reciprocal).
+    T n0 = q1 * q2, n1 = T(6) * q0 * q2, n2 = T(3) * q0 * q1;
+    T inv = frcp(n0 + n1 + n2);
+    // eq. (2): omega_0 (a-2b+c)/3 + (omega_2 - 1/2)(b-2c+d)/6
+    T x3 = (a - T(2) * b + c) * T(1.0 / 3.0);
+    T y6 = (b - T(2) * c + d) * T(1.0 / 6.0);
+    return fma(inv, fma(n0, x3, n2 * y6), T(-0.5) * y6);
+}
+
+// eq. (1) for one field.  cc: projected central term; df, du: projected flux
+// and state differences (k = 0..4 at i-3/2 .. i+5/2), both already carrying
+// the 1/2 of the Lax-Friedrichs split; al: LF speed.
+template <typename T>
+__device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps)
+{
+    T dp[5], dm[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        dp[k] = fma(al, du[k], df[k]);
+        dm[k] = fma(-al, du[k], df[k]);
+    }
+    return cc - phi_n(dp[0], dp[1], dp[2], dp[3], eps) + phi_n(dm[4], dm[3], dm[2], dm[1], eps);
+}
+
+// Stage one cell: sweep-frame conserved variables and derived quantities.
+template <typename T>
+__device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, long sv,
+                                           const int (&cm)[8], double gamma, T *q, int qs)
+{
+    T r = u[id + cm[0] * sv], mn = u[id + cm[1] * sv], m1 = u[id + cm[2] * sv],
+      m2 = u[id + cm[3] * sv], bn = u[id + cm[4] * sv], b1 = u[id + cm[5] * sv],
+      b2 = u[id + cm[6] * sv], e = u[id + cm[7] * sv];
+    // pressure recovery (kept in FP64 for every storage type)
+    double ird = frcp((double)r);
+    double pd = (gamma - 1.0) * ((double)e - 0.5 * ((double)mn * mn + (double)m1 * m1 + (double)m2 * m2) * ird
+                                 - 0.5 * ((double)bn * bn + (double)b1 * b1 + (double)b2 * b2));
+    T p = (T)pd;
+    T ir = (T)ird;
+    T a2 = T(gamma) * p * ir;
+    T bn2 = bn * bn * ir;
+    T bt2 = (b1 * b1 + b2 * b2) * ir;
+    T dd = a2 - bn2;
+    T disc = dd * dd + bt2 * (T(2) * a2 + T(2) * bn2 + bt2);
+    T cf2 = T(0.5) * (a2 + bn2 + bt2 + sqrt(disc));
+    T cs2 = a2 * bn2 * frcp(cf2);
+    q[0 * qs] = r;  q[1 * qs] = mn; q[2 * qs] = m1; q[3 * qs] = m2;
+    q[4 * qs] = bn; q[5 * qs] = b1; q[6 * qs] = b2; q[7 * qs] = e;
+    q[8 * qs] = p;
+    q[9 * qs] = ir;
+    q[10 * qs] = sqrt(cf2);
+    q[11 * qs] = sqrt(cs2);
+    q[12 * qs] = sqrt(bn2);
+}
+
+// Interface flux from six staged cells.  sq: LDS base, qs: stride between
+// quantities, off: offset of cell i-2, cstr: stride between cells.
+// out: sweep-frame flux (rho, mn, mt1, mt2, Bt1, Bt2, E).
+template <typename T>
+__device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
+                                          double gamma, double igm1, T eps, T (&out)[7])
+{
+#define QQ(q, j) sq[(q) * qs + off + (j) * cstr]
+    T C[7], dY[5][7], dZ[5][7], am[7];
+    T Fp[7], Up[7];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        T r = QQ(0, j), mn = QQ(1, j), m1 = QQ(2, j), m2 = QQ(3, j);
+        T bn = QQ(4, j), b1 = QQ(5, j), b2 = QQ(6, j), e = QQ(7, j);
+        T p = QQ(8, j), ir = QQ(9, j), cf = QQ(10, j), cs = QQ(11, j), ca = QQ(12, j);
+        T vn = mn * ir, v1 = m1 * ir, v2 = m2 * ir;
+        T pt = p + T(0.5) * (bn * bn + b1 * b1 + b2 * b2);
+        T Fj[7] = { mn, mn * vn + pt - bn * bn, m1 * vn - bn * b1, m2 * vn - bn * b2,
+                    vn * b1 - v1 * bn, vn * b2 - v2 * bn,
+                    (e + pt) * vn - bn * (vn * bn + v1 * b1 + v2 * b2) };
+        T Uj[7] = { r, mn, m1, m2, b1, b2, e };
+        T lam[7] = { fabs(vn - cf), fabs(vn - ca), fabs(vn - cs), fabs(vn),
+                     fabs(vn + cs), fabs(vn + ca), fabs(vn + cf) };
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            am[c] = (j == 0) ? lam[c] : fmax(am[c], lam[c]);
+            if (j == 1) C[c] = -Fj[c];
+            if (j == 2 || j == 3) C[c] += T(7) * Fj[c];
+            if (j == 4) C[c] = (C[c] - Fj[c]) * T(1.0 / 6.0);   // twice the central term
+            if (j > 0) { dY[j - 1][c] = Fj[c] - Fp[c]; dZ[j - 1][c] = Uj[c] - Up[c]; }
+            Fp[c] = Fj[c];
+            Up[c] = Uj[c];
+        }
+    }
+
+    // Interface state: mean of the primitive variables of cells i and i+1.
+    // Eigen-system normalisation in FP64 for every storage type.
+    double r2 = QQ(0, 2), r3 = QQ(0, 3), i2 = QQ(9, 2), i3 = QQ(9, 3);
+    double rb = 0.5 * (r2 + r3);
+    double vnb = 0.5 * ((double)QQ(1, 2) * i2 + (double)QQ(1, 3) * i3);
+    double v1b = 0.5 * ((double)QQ(2, 2) * i2 + (double)QQ(2, 3) * i3);
+    double v2b = 0.5 * ((double)QQ(3, 2) * i2 + (double)QQ(3, 3) * i3);
+    double bnb = 0.5 * ((double)QQ(4, 2) + (double)QQ(4, 3));
+    double b1b = 0.5 * ((double)QQ(5, 2) + (double)QQ(5, 3));
+    double b2b = 0.5 * ((double)QQ(6, 2) + (double)QQ(6, 3));
+    double pb = 0.5 * ((double)QQ(8, 2) + (double)QQ(8, 3));
+#undef QQ
+    double irb = frcp(rb);
+    double a2 = gamma * pb * irb;
+    double bn2 = bnb * bnb * irb;
+    double bt2 = (b1b * b1b + b2b * b2b) * irb;
+    double dd = a2 - bn2;
+    double sqD = sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2));
+    double cf2 = 0.5 * (a2 + bn2 + bt2 + sqD);
+    double icf2 = frcp(cf2);
+    double cs2 = a2 * bn2 * icf2;
+    double af, as;
+    if (sqD <= 1e-12 * (a2 + bn2 + bt2)) {
+        af = 1.0; as = 0.0;
+    } else {
+        // (cf^2 - a^2)(cf^2 - bn^2) = bt^2 cf^2 avoids the cancellation
+        double P, Q;
+        if (dd >= 0.0) { P = 0.5 * (dd + bt2 + sqD); Q = bt2 * cf2 * frcp(P); }
+        else           { Q = 0.5 * (-dd + bt2 + sqD); P = bt2 * cf2 * frcp(Q); }
+        double isq = frcp(sqD);
+        double af2 = fmin(fmax(a2 * P * icf2 * isq, 0.0), 1.0);
+        double as2 = fmin(fmax(Q * isq, 0.0), 1.0);
+        af = sqrt(af2); as = sqrt(as2);
+    }
+    double be1, be2;
+    if (bt2 > 1e-24 * (a2 + bn2)) {
+        double ibt = frcp(sqrt(b1b * b1b + b2b * b2b));
+        be1 = b1b * ibt; be2 = b2b * ibt;
+    } else {
+        be1 = be2 = 0.70710678118654752440;
+    }
+    double sg = (bnb >= 0.0) ? 1.0 : -1.0;
+    double cfm = sqrt(cf2), csm = sqrt(cs2), am_ = sqrt(a2), sr = sqrt(rb);
+    double isr = frcp(sr), ia2 = frcp(a2);
+    double gm1 = gamma - 1.0;
+    double hv2 = 0.5 * (vnb * vnb + v1b * v1b + v2b * v2b);
+
+    // rows of L_W, per wave pair: odd (sign-flipping) and even parts, with
+    // the 1/2 of the Lax-Friedrichs split folded in (exact power-of-two scale)
+    const T i2a2 = T(0.25 * ia2);
+    const T kf1 = T(af * cfm) * i2a2, kf2 = T(as * csm * sg) * i2a2;
+    const T kf4 = T(as * am_ * isr) * i2a2, kf6 = T(af * irb) * i2a2;
+    const T ks1 = T(as * csm) * i2a2, ks2 = T(af * cfm * sg) * i2a2;
+    const T ks4 = T(af * am_ * isr) * i2a2, ks6 = T(as * irb) * i2a2;
+    const T ka3 = T(0.25 * sg), ka5 = T(0.25 * isr), ke6 = T(ia2), kh = T(0.5);
+
+    // dW/dU at the interface state followed by the rotation of the
+    // transverse components onto (beta, perpendicular).
+    const T tv = T(vnb), t1 = T(v1b), t2 = T(v2b), tir = T(irb), tg = T(gm1), th = T(hv2);
+    const T tb1 = T(b1b), tb2 = T(b2b), e1 = T(be1), e2 = T(be2);
+    auto xf = [&](T (&X)[7]) {
+        T w1 = (X[1] - tv * X[0]) * tir;
+        T w2 = (X[2] - t1 * X[0]) * tir;
+        T w3 = (X[3] - t2 * X[0]) * tir;
+        T w6 = tg * (th * X[0] - tv * X[1] - t1 * X[2] - t2 * X[3] - tb1 * X[4] - tb2 * X[5] + X[6]);
+        T pv = e1 * w2 + e2 * w3, qv = e2 * w2 - e1 * w3;
+        T pB = e1 * X[4] + e2 * X[5], qB = e1 * X[5] - e2 * X[4];
+        X[1] = w1; X[2] = pv; X[3] = qv; X[4] = pB; X[5] = qB; X[6] = w6;
+    };
+    xf(C);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { xf(dY[k]); xf(dZ[k]); }
+
+    T G[7] = { T(0), T(0), T(0), T(0), T(0), T(0), T(0) };
+    const T teps = T(0.25) * eps;     // epsilon / 4 for phi_n
+
+    // One wave pair (sigma = -1 field index lo, sigma = +1 field index hi).
+    // proj(X, odd, even) gives the odd and even parts of the row applied to X.
+    auto pair = [&](auto proj, int lo, int hi, T &S, T &D) {
+        T oc, ec, odf[5], edf[5], odu[5], edu[5];
+        proj(C, oc, ec);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) { proj(dY[k], odf[k], edf[k]); proj(dZ[k], odu[k], edu[k]); }
+        T df[5], du[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) { df[k] = edf[k] + odf[k]; du[k] = edu[k] + odu[k]; }
+        T fplus = weno_field(ec + oc, df, du, am[hi], teps);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) { df[k] = edf[k] - odf[k]; du[k] = edu[k] - odu[k]; }
+        T fminus = weno_field(ec - oc, df, du, am[lo], teps);
+        S = fplus + fminus;
+        D = fplus - fminus;
+    };
+
+    T S, D;
+    // fast pair (fields 0 and 6)
+    pair([&](const T (&X)[7], T &o, T &e) { o = kf1 * X[1] - kf2 * X[2]; e = kf4 * X[4] + kf6 * X[6]; },
+         0, 6, S, D);
+    {
+        const T c0 = T(rb * af), c1 = T(af * cfm), c2 = T(-as * csm * sg), c4 = T(as * sr * am_),
+                c6 = T(rb * af * a2);
+        G[0] += c0 * S; G[1] += c1 * D; G[2] += c2 * D; G[4] += c4 * S; G[6] += c6 * S;
+    }
+    // slow pair (fields 2 and 4)
+    pair([&](const T (&X)[7], T &o, T &e) { o = ks1 * X[1] + ks2 * X[2]; e = ks6 * X[6] - ks4 * X[4]; },
+         2, 4, S, D);
+    {
+        const T c0 = T(rb * as), c1 = T(as * csm), c2 = T(af * cfm * sg), c4 = T(-af * sr * am_),
+                c6 = T(rb * as * a2);
+        G[0] += c0 * S; G[1] += c1 * D; G[2] += c2 * D; G[4] += c4 * S; G[6] += c6 * S;
+    }
+    // Alfven pair (fields 1 and 5)
+    pair([&](const T (&X)[7], T &o, T &e) { o = ka3 * X[3]; e = ka5 * X[5]; }, 1, 5, S, D);
+    G[3] += T(sg) * D;
+    G[5] += T(sr) * S;
+    // entropy (field 3)
+    {
+        T cc = kh * (C[0] - ke6 * C[6]), df[5], du[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            df[k] = kh * (dY[k][0] - ke6 * dY[k][6]);
+            du[k] = kh * (dZ[k][0] - ke6 * dZ[k][6]);
+        }
+        G[0] += weno_field(cc, df, du, am[3], teps);
+    }
+
+    // back to (vt1, vt2), (Bt1, Bt2) and through dU/dW
+    T gv1 = e1 * G[2] + e2 * G[3], gv2 = e2 * G[2] - e1 * G[3];
+    T gb1 = e1 * G[4] - e2 * G[5], gb2 = e2 * G[4] + e1 * G[5];
+    const T trb = T(rb);
+    out[0] = G[0];
+    out[1] = tv * G[0] + trb * G[1];
+    out[2] = t1 * G[0] + trb * gv1;
+    out[3] = t2 * G[0] + trb * gv2;
+    out[4] = gb1;
+    out[5] = gb2;
+    out[6] = th * G[0] + trb * (tv * G[1] + t1 * gv1 + t2 * gv2) + tb1 * gb1 + tb2 * gb2
+           + G[6] * T(igm1);
+}
+
+// Store a sweep-frame interface flux in grid components:
+// rho, mx, my, mz, B_(N+1), B_(N+2), E.
+template <int N, typename T>
+__device__ __forceinline__ void store_face(T *__restrict__ flux, const FaceBox &F, const int (&pos)[3],
+                                           const T (&out)[7])
+{
+    constexpr int T1 = (N + 1) % 3, T2 = (N + 2) % 3;
+    const long fi = F.idx(pos[0], pos[1], pos[2]);
+    flux[0 * F.sc + fi] = out[0];
+    flux[(1 + N) * F.sc + fi] = out[1];
+    flux[(1 + T1) * F.sc + fi] = out[2];
+    flux[(1 + T2) * F.sc + fi] = out[3];
+    flux[4 * F.sc + fi] = out[4];
+    flux[5 * F.sc + fi] = out[5];
+    flux[6 * F.sc + fi] = out[6];
+}
+
+// One tile of interfaces along axis DIR.  x sweep: ROWS rows (transverse
+// (j,k) pairs, tile index ta) x TILE consecutive faces (tile index tb).
+// y/z sweeps: TILE consecutive positions of the transverse plane (x fastest,
+// tile index ta) x FT consecutive faces (tile index tb); each of the ROWS
+// waves computes faces w, w+ROWS, ...  sq: LDS of NQ * tile_cells<DIR,FT>()
+// elements.  Ends with a block barrier, so consecutive tiles may reuse sq.
+template <int DIR, int FT>
+__host__ __device__ constexpr int tile_cells() { return DIR == 0 ? ROWS * NCX : TILE * (FT + 5); }
+
+template <int DIR, int FT, typename T>
+__device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restrict__ flux,
+                                           const Geom &G, const FaceBox &F, const Phys &P,
+                                           int ta, int tb, T *sq)
+{
+    constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+    const int cm[8] = { 0, 1 + N, 1 + T1, 1 + T2, 4 + N, 4 + T1, 4 + T2, 7 };
+    constexpr int NC = tile_cells<DIR, FT>();
+    const int lane = threadIdx.x, w = threadIdx.y, tid = lane + TILE * w;
+    const int nlast = G.n[N] + 2;   // last cell index along the sweep axis
+
+    if constexpr (DIR == 0) {
+        const int nrows = F.cnt[1] * F.cnt[2];
+        const int r0 = ta * ROWS;
+        const int f0 = tb * TILE;
+        for (int c = tid; c < ROWS * NCX; c += TILE * ROWS) {
+            int rr = c / NCX, xi = c - rr * NCX;
+            int row = r0 + rr;
+            int x = f0 - 3 + xi;
+            if (row < nrows && x <= nlast) {
+                int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
+                long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
+                stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+            }
+        }
+        __syncthreads();
+        const int row = r0 + w;
+        int pos[3];
+        pos[0] = f0 + lane;
+        pos[1] = F.lo[1] + row % F.cnt[1];
+        pos[2] = F.lo[2] + row / F.cnt[1];
+        if (row < nrows && pos[0] < F.cnt[0]) {
+            T out[7];
+            face_flux<T>(sq, NC, w * NCX + lane, 1, P.gamma, P.igm1, (T)P.eps, out);
+            store_face<N, T>(flux, F, pos, out);
+        }
+    } else {
+        // positions in the transverse plane (x fastest, then the other axis)
+        constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
+        const int npos = F.cnt[A] * F.cnt[B];
+        const int p = ta * TILE + lane;
+        const int f0 = tb * FT;
+        const int ca = F.lo[A] + p % F.cnt[A], cb = F.lo[B] + p / F.cnt[A];
+        for (int rr = w; rr < FT + 5; rr += ROWS) {
+            int y = f0 - 3 + rr;
+            if (p < npos && y <= nlast) {
+                long id = G.base + ca * G.s[A] + cb * G.s[B] + (long)y * G.s[N];
+                stage_cell(u, id, G.sv, cm, P.gamma, sq + rr * TILE + lane, NC);
+            }
+        }
+        __syncthreads();
+        for (int ff = w; ff < FT; ff += ROWS) {
+            int pos[3];
+            pos[A] = ca;
+            pos[B] = cb;
+            pos[N] = f0 + ff;
+            if (p < npos && pos[N] < F.cnt[N]) {
+                T out[7];
+                face_flux<T>(sq, NC, ff * TILE + lane, TILE, P.gamma, P.igm1, (T)P.eps, out);
+                store_face<N, T>(flux, F, pos, out);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// x sweep for short rows (batched patches): the block takes XF_FACES
+// consecutive faces of the flattened (row, face) space, stages every cell of
+// the rows they touch (-3..n+2), and each thread computes one face.  The
+// rows touched hold at most xflat_cells(n, rows) cells; sq needs
+// NQ * XF_MAXC elements.
+constexpr int XF_FACES = TILE * ROWS;
+constexpr int XF_MAXC = 448;
+__host__ __device__ inline int xflat_cells(int nx, long nrows)
+{
+    long span = (XF_FACES + nx) / (nx + 1) + 1;
+    if (span > nrows) span = nrows;
+    return (int)(span * (nx + 6));
+}
+
+template <typename T>
+__device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__restrict__ flux,
+                                                 const Geom &G, const FaceBox &F, const Phys &P,
+                                                 long tile, T *sq)
+{
+    const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
+    const int nf = F.cnt[0], rowc = G.n[0] + 6;
+    const long nrows = (long)F.cnt[1] * F.cnt[2];
+    const long g0 = tile * XF_FACES;
+    const long r_lo = g0 / nf;
+    long r_hi = (g0 + XF_FACES - 1) / nf;
+    if (r_hi > nrows - 1) r_hi = nrows - 1;
+    const int ncell = (int)(r_hi - r_lo + 1) * rowc;
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    for (int c = tid; c < ncell; c += XF_FACES) {
+        long row = r_lo + c / rowc;
+        int x = c % rowc - 3;
+        int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
+        long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
+        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XF_MAXC);
+    }
+    __syncthreads();
+    const long g = g0 + tid;
+    if (g < nrows * nf) {
+        const long row = g / nf;
+        const int f = (int)(g - row * nf);
+        int pos[3];
+        pos[0] = f;
+        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
+        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
+        T out[7];
+        // stencil cells f-3 .. f+2 sit at row offset f .. f+5
+        face_flux<T>(sq, XF_MAXC, (int)(row - r_lo) * rowc + f, 1, P.gamma, P.igm1, (T)P.eps, out);
+        store_face<0, T>(flux, F, pos, out);
+    }
+    __syncthreads();
+}
+
+// Number of tiles (ta, tb) of a sweep.
+template <int DIR, int FT>
+__host__ __device__ inline void sweep_tiles(const FaceBox &F, long &na, long &nb)
+{
+    if (DIR == 0) {
+        na = ((long)F.cnt[1] * F.cnt[2] + ROWS - 1) / ROWS;
+        nb = (F.cnt[0] + TILE - 1) / TILE;
+    } else {
+        constexpr int B = (DIR == 1) ? 2 : 1;
+        na = ((long)F.cnt[0] * F.cnt[B] + TILE - 1) / TILE;
+        nb = (F.cnt[DIR] + FT - 1) / FT;
+    }
+}
+
+}  // namespace sw
+}  // namespace ww

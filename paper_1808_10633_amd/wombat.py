@@ -76,6 +76,20 @@ def lib():
         L.wombat_weno_sums.argtypes = [vp, vp, C.POINTER(d)]
         L.wombat_weno_divb.argtypes = [vp, vp, C.POINTER(d), C.POINTER(d)]
         L.wombat_weno_time_kernels.argtypes = [vp, vp, i32, C.POINTER(d)]
+        L.wombat_weno_batch_init.argtypes = [C.POINTER(Config), i32, C.POINTER(C.c_int32), C.POINTER(vp)]
+        L.wombat_weno_batch_destroy.argtypes = [vp]
+        L.wombat_weno_batch_destroy.restype = None
+        L.wombat_weno_batch_last_error.argtypes = [vp]
+        L.wombat_weno_batch_last_error.restype = C.c_char_p
+        L.wombat_weno_batch_arena_elems.argtypes = [vp]
+        L.wombat_weno_batch_arena_elems.restype = C.c_int64
+        L.wombat_weno_batch_patch_offset.argtypes = [vp, i32]
+        L.wombat_weno_batch_patch_offset.restype = C.c_int64
+        L.wombat_weno_batch_step.argtypes = [vp, vp]
+        L.wombat_weno_batch_graph_steps.argtypes = [vp, vp, i32]
+        L.wombat_weno_batch_dt.argtypes = [vp, vp, vp]
+        L.wombat_weno_batch_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.wombat_weno_batch_autotune.argtypes = [vp, vp, C.c_char_p, C.POINTER(d)]
         _lib = L
     return _lib
 
@@ -196,3 +210,90 @@ class Context:
         mx, l1 = C.c_double(), C.c_double()
         _check(lib().wombat_weno_divb(self.h, self._ptr(u, "u"), C.byref(mx), C.byref(l1)), self.h)
         return mx.value, l1.value
+
+
+class Batch:
+    """Many independent periodic patches in one arena (``wombat_weno_batch_t``).
+
+    ``dims``: sequence of (nx, ny, nz) per patch.  The arena is a 1-D contiguous
+    CUDA tensor of ``arena_elems`` elements; ``view(arena, p)`` gives patch p's
+    padded state (8, nz+6, ny+6, nx+6).
+    """
+
+    def __init__(self, dims, dx, precision=WW_FP32_MIXED, gamma=5.0 / 3.0, cfl=0.4, eps=1e-6,
+                 stream=None, device=None):
+        import numpy as np
+        import torch
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        cfg = make_config(8, 8, 8, dx=dx, dy=dx, dz=dx, gamma=gamma, cfl=cfl, eps=eps,
+                          precision=precision,
+                          stream=torch.cuda.current_stream().cuda_stream if stream is None else stream,
+                          device=torch.cuda.current_device() if device is None else device)
+        self.cfg = cfg
+        arr = np.ascontiguousarray(np.array(self.dims, dtype=np.int32).reshape(-1))
+        h = C.c_void_p()
+        rc = lib().wombat_weno_batch_init(C.byref(cfg), len(self.dims),
+                                          arr.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h))
+        if rc != WW_OK:
+            raise WenoError(rc, lib().wombat_weno_batch_last_error(None).decode())
+        self.h = h
+        self.dtype = torch.float64 if precision == WW_FP64 else torch.float32
+        self.arena_elems = int(lib().wombat_weno_batch_arena_elems(h))
+        self.offsets = [int(lib().wombat_weno_batch_patch_offset(h, p)) for p in range(len(self.dims))]
+
+    def _check(self, rc):
+        if rc != WW_OK:
+            raise WenoError(rc, lib().wombat_weno_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wombat_weno_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_arena(self):
+        import torch
+        return torch.zeros(self.arena_elems, dtype=self.dtype, device=f"cuda:{self.cfg.device}")
+
+    def view(self, arena, p):
+        nx, ny, nz = self.dims[p]
+        n = 8 * (nx + 6) * (ny + 6) * (nz + 6)
+        o = self.offsets[p]
+        return arena[o:o + n].view(8, nz + 6, ny + 6, nx + 6)
+
+    def _ptr(self, arena):
+        if (not arena.is_cuda or arena.dtype != self.dtype or arena.numel() != self.arena_elems
+                or not arena.is_contiguous()):
+            raise ValueError("arena: need a contiguous cuda tensor of arena_elems elements")
+        return C.c_void_p(arena.data_ptr())
+
+    def step(self, arena):
+        self._check(lib().wombat_weno_batch_step(self.h, self._ptr(arena)))
+
+    def graph_steps(self, arena, nsteps):
+        self._check(lib().wombat_weno_batch_graph_steps(self.h, self._ptr(arena), int(nsteps)))
+
+    def dt(self):
+        import numpy as np
+        d = np.zeros(len(self.dims))
+        f = np.zeros(len(self.dims), dtype=np.int32)
+        self._check(lib().wombat_weno_batch_dt(self.h, d.ctypes.data_as(C.c_void_p),
+                                               f.ctypes.data_as(C.c_void_p)))
+        return d, f
+
+    def shape(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(lib().wombat_weno_batch_shape(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, arena, cache_path=None):
+        ms = C.c_double()
+        self._check(lib().wombat_weno_batch_autotune(self.h, self._ptr(arena),
+                                                     cache_path.encode() if cache_path else None,
+                                                     C.byref(ms)))
+        return ms.value
