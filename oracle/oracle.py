@@ -98,6 +98,8 @@ def lib():
         L.orc_wave_speeds.argtypes = [_dp, C.c_int, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
         L.orc_eigensystem.argtypes = [_dp, d, _dp, _dp, _dp]
         L.orc_interface_flux.argtypes = [_dp, d, d, _dp]
+        L.orc_interface_flux_ex.argtypes = [_dp, d, d, C.c_int, _dp, C.POINTER(d)]
+        L.orc_linear_flux.argtypes = [_dp, d, _dp]
         g = C.POINTER(_Grid)
         L.orc_state_size.argtypes = [g]
         L.orc_state_size.restype = C.c_long
@@ -173,6 +175,21 @@ def eigensystem(Wn, gamma=5.0 / 3.0):
 def interface_flux(Us, gamma=5.0 / 3.0, eps=1e-6):
     F = np.zeros(8)
     lib().orc_interface_flux(_f64(np.asarray(Us).reshape(48)), gamma, eps, F)
+    return F
+
+
+def interface_flux_ex(Us, gamma=5.0 / 3.0, eps=1e-6, common_alpha=False):
+    """(flux, largest weight deviation from linear) at one interface."""
+    F = np.zeros(8)
+    dev = C.c_double()
+    lib().orc_interface_flux_ex(_f64(np.asarray(Us).reshape(48)), gamma, eps, int(common_alpha), F,
+                                C.byref(dev))
+    return F, dev.value
+
+
+def linear_flux(Us, gamma=5.0 / 3.0):
+    F = np.zeros(8)
+    lib().orc_linear_flux(_f64(np.asarray(Us).reshape(48)), gamma, F)
     return F
 
 

@@ -327,9 +327,33 @@ void orc_eigensystem(const double Wn[8], double gamma,
     L[7 * 8 + 4] = 1.0;
 }
 
-/* Characteristic WENO flux at the interface i+1/2 between Us row 2 and 3. */
-void orc_interface_flux(const double Us[48], double gamma, double eps,
-                        double Fhat[8])
+/* Largest deviation of the nonlinear weights of eq. (3) from the linear
+ * weights (0.1, 0.6, 0.3) for the two phi_N of eq. (1) of one field. */
+static double weight_deviation(const double f[6], const double u[6], double alpha,
+                               double eps)
+{
+    double fp[6], fm[6], dp[5], dm[5], w[3], dev = 0.0;
+    static const double d[3] = { 0.1, 0.6, 0.3 };
+    int j, k;
+    for (j = 0; j < 6; ++j) {
+        fp[j] = 0.5 * (f[j] + alpha * u[j]);
+        fm[j] = 0.5 * (f[j] - alpha * u[j]);
+    }
+    for (j = 0; j < 5; ++j) { dp[j] = fp[j + 1] - fp[j]; dm[j] = fm[j + 1] - fm[j]; }
+    orc_weno_weights(dp[0], dp[1], dp[2], dp[3], eps, w, NULL);
+    for (k = 0; k < 3; ++k) if (fabs(w[k] - d[k]) > dev) dev = fabs(w[k] - d[k]);
+    orc_weno_weights(dm[4], dm[3], dm[2], dm[1], eps, w, NULL);
+    for (k = 0; k < 3; ++k) if (fabs(w[k] - d[k]) > dev) dev = fabs(w[k] - d[k]);
+    return dev;
+}
+
+/* Characteristic WENO flux with options: common_alpha = 0 uses the per-field
+ * LF speed max|lambda^s| (the reading used everywhere else); 1 uses one speed
+ * max(|v_n| + c_f) over the stencil for every field.  *dev (may be NULL)
+ * receives the largest deviation of any weight of any field from the linear
+ * weights -- the label of a troubled interface. */
+void orc_interface_flux_ex(const double Us[48], double gamma, double eps,
+                           int common_alpha, double Fhat[8], double *dev)
 {
     double F[6][8], lamc[6][8], W[6][8], Wm[8], lam[8], L[64], R[64], Fs[8];
     int j, c, s;
@@ -347,6 +371,11 @@ void orc_interface_flux(const double Us[48], double gamma, double eps,
     }
     for (c = 0; c < 8; ++c) Wm[c] = 0.5 * (W[2][c] + W[3][c]);
     orc_eigensystem(Wm, gamma, lam, L, R);
+    double acommon = 0.0, dmax = 0.0;
+    for (j = 0; j < 6; ++j) {
+        double a = fabs(lamc[j][0] - W[j][1]) + fabs(W[j][1]);   /* c_f + |v_n| */
+        if (a > acommon) acommon = a;
+    }
     for (s = 0; s < 8; ++s) {
         double fs[6], us[6], alpha = 0.0;
         for (j = 0; j < 6; ++j) {
@@ -359,13 +388,55 @@ void orc_interface_flux(const double Us[48], double gamma, double eps,
             us[j] = b;
             if (fabs(lamc[j][s]) > alpha) alpha = fabs(lamc[j][s]);
         }
+        if (common_alpha && s < 7) alpha = acommon;   /* the B_n identity row keeps 0 */
         Fs[s] = orc_weno_field_flux(fs, us, alpha, eps);
+        if (dev && s < 7) {
+            double dv = weight_deviation(fs, us, alpha, eps);
+            if (dv > dmax) dmax = dv;
+        }
     }
+    if (dev) *dev = dmax;
     for (c = 0; c < 8; ++c) {
         double a = 0.0;
         for (s = 0; s < 8; ++s) a += R[c * 8 + s] * Fs[s];
         Fhat[c] = a;
     }
+}
+
+/* Characteristic WENO flux at the interface i+1/2 between Us row 2 and 3. */
+void orc_interface_flux(const double Us[48], double gamma, double eps,
+                        double Fhat[8])
+{
+    orc_interface_flux_ex(Us, gamma, eps, 0, Fhat, NULL);
+}
+
+/* Linear fifth-order component-wise flux (the cheap flux of interfaces the
+ * learned router calls smooth): Lax-Friedrichs split of every conserved
+ * component with one speed alpha = max over the stencil of |v_n| + c_f, and
+ * the linear-weight form of eq. (1),
+ *   F^+: (2, -13, 47, 27, -3)/60 on cells i-2..i+2,
+ *   F^-: (-3, 27, 47, -13, 2)/60 on cells i-1..i+3. */
+void orc_linear_flux(const double Us[48], double gamma, double Fhat[8])
+{
+    double F[6][8], alpha = 0.0;
+    int j, c;
+    for (j = 0; j < 6; ++j) {
+        double W[8], cf, ca, cs;
+        orc_cons_to_prim(Us + 8 * j, gamma, W);
+        orc_flux(Us + 8 * j, 0, gamma, F[j]);
+        orc_wave_speeds(Us + 8 * j, 0, gamma, &cf, &ca, &cs);
+        if (fabs(W[1]) + cf > alpha) alpha = fabs(W[1]) + cf;
+    }
+    for (c = 0; c < 8; ++c) {
+        double p[6], m[6];
+        for (j = 0; j < 6; ++j) {
+            p[j] = 0.5 * (F[j][c] + alpha * Us[8 * j + c]);
+            m[j] = 0.5 * (F[j][c] - alpha * Us[8 * j + c]);
+        }
+        Fhat[c] = (2.0 * p[0] - 13.0 * p[1] + 47.0 * p[2] + 27.0 * p[3] - 3.0 * p[4]) / 60.0
+                + (-3.0 * m[1] + 27.0 * m[2] + 47.0 * m[3] - 13.0 * m[4] + 2.0 * m[5]) / 60.0;
+    }
+    Fhat[4] = 0.0;     /* the normal field has no flux */
 }
 
 /* ------------------------------------------------------------------------ */

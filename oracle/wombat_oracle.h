@@ -59,6 +59,14 @@ void orc_eigensystem(const double Wn[8], double gamma,
  * Writes the sweep-frame interface flux at i+1/2. */
 void orc_interface_flux(const double Us[48], double gamma, double eps,
                         double Fhat[8]);
+/* As orc_interface_flux; common_alpha = 1 uses one LF speed
+ * max(|v_n| + c_f) for every field; *dev (may be NULL) receives the largest
+ * deviation of the weights of eq. (3) from (0.1, 0.6, 0.3) over all fields
+ * and both sides. */
+void orc_interface_flux_ex(const double Us[48], double gamma, double eps,
+                           int common_alpha, double Fhat[8], double *dev);
+/* Linear fifth-order component-wise flux with one LF speed (see the C file). */
+void orc_linear_flux(const double Us[48], double gamma, double Fhat[8]);
 
 /* ---- grid operations ---- */
 long   orc_state_size(const orc_grid *g);          /* doubles in one state */
