@@ -53,6 +53,13 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 precision form")
     ap.add_argument("--batch-patches", type=int, default=4096,
                     help="patches of the batched form (0 skips it)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-router form")
+    ap.add_argument("--learned-n", type=int, default=512)
+    ap.add_argument("--train-n", type=int, default=256)
+    ap.add_argument("--pre-steps", type=int, default=200,
+                    help="full-WENO FP32 steps that shock the learned-form turbulence")
+    ap.add_argument("--learned-steps", type=int, default=50)
+    ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the event timing")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -138,6 +145,141 @@ def batched_form(a, wombat, inputs, opcount):
                         "flop_per_interface": opcount.flops_per_interface(),
                         "interfaces_per_launch": faces, "kernel_ms": stage_ms}}
     del bt, ar
+    return res
+
+
+def shocked_turbulence(n, seed, wombat, inputs, pre, snaps=()):
+    """Supersonic turbulence (rms Mach 3, beta 10, 10 % of the kinetic energy
+    compressive, log-normal density sigma 0.5, p = 1), advanced `pre` full
+    characteristic WENO FP32 steps at CFL 0.4.  Yields (step, context, state)
+    after each step listed in snaps and at the end."""
+    u = inputs.turbulence((n, n, n), mach=3.0, beta=10.0, seed=seed, compressive_fraction=0.1,
+                          lognormal_sigma=0.5, device="cuda").float().contiguous()
+    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4)
+    for s in range(1, pre + 1):
+        ctx.step(u, 0.0)
+        if s in snaps and s != pre:
+            yield s, ctx, u
+    yield pre, ctx, u
+
+
+def rel_errors(a, b, sl):
+    """Per-variable relative L1 and Linf of a against b on the interior."""
+    l1, linf = [], []
+    for v in range(8):
+        d = (a[sl][v].double() - b[sl][v].double()).abs()
+        ref = b[sl][v].double().abs()
+        if float(ref.max()) > 0:
+            l1.append(float(d.mean() / ref.mean()))
+            linf.append(float(d.max() / ref.max()))
+    return max(l1), max(linf)
+
+
+def learned_form(a, wombat, inputs, router):
+    """Learned-router form on shocked Mach-3 turbulence.  Training: the same
+    recipe at train_n^3, seeds 5001-5004, snapshots after half and all of
+    the pre-steps scaled to the same physical time (pre * train_n / n steps),
+    interfaces sampled at random (features and flux-excess labels from the
+    library), MLP trained by the library's BF16 MFMA kernels, threshold set
+    for <= 2 % false-smooth on the training set.  Evaluation: seed 5000 at
+    learned_n^3 after pre steps; from that snapshot `learned_steps` steps of
+    full WENO and of the learned route (the full run's step sizes replayed),
+    compared to each other, and the all-linear route (no network) as the
+    accuracy floor."""
+    import torch
+    t0 = time.perf_counter()
+    Xs, ts = [], []
+    pre_tr = max(2, round(a.pre_steps * a.train_n / a.learned_n))
+    for seed in (5001, 5002, 5003, 5004):
+        for step, ctx, u in shocked_turbulence(a.train_n, seed, wombat, inputs, pre_tr,
+                                               snaps=(pre_tr // 2,)):
+            X, _, _, t = router.sample(ctx, u, 250000, seed=seed * 10 + step)
+            Xs.append(X)
+            ts.append(t)
+        del ctx, u
+    X = torch.cat(Xs)
+    t = torch.cat(ts)
+    del Xs, ts
+    nval = X.shape[0] // 10
+    perm = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(0)).cuda()
+    X, t = X[perm], t[perm]
+    Xtr, ttr, Xva, tva = X[nval:], t[nval:], X[:nval], t[:nval]
+    print(f"[bench] learned: {X.shape[0]} training interfaces in {time.perf_counter() - t0:.1f} s, "
+          f"troubled fraction {float(t.mean()):.3f}", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    theta, hist = router.train(Xtr, ttr, steps=a.train_steps, batch=4096, lr=2e-3, seed=1,
+                               log_every=max(a.train_steps // 10, 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    thr = router.choose_threshold(theta, Xtr, ttr, max_false_smooth=0.02)
+    val = router.evaluate(theta, Xva, tva, thr)
+    print(f"[bench] learned: trained in {train_s:.1f} s, loss {hist[0][1]:.3f} -> {hist[-1][1]:.3f}, "
+          f"threshold {thr:.3g}", file=sys.stderr, flush=True)
+    del X, t, Xtr, ttr, Xva, tva
+
+    n = a.learned_n
+    for _, ctx, u in shocked_turbulence(n, 5000, wombat, inputs, a.pre_steps):
+        pass
+    Xe, deve, _, te = router.sample(ctx, u, 250000, seed=50000)
+    ev = router.evaluate(theta, Xe, te, thr)
+    ev["weight_deviation_above_1e-2"] = float((deve > 1e-2).float().mean())
+    del Xe, te, deve
+    snap = u.clone()
+    sl = inputs.interior_slices(n, n, n)
+    nsteps = a.learned_steps
+    dts = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        dts.append(ctx.step(u, 0.0))
+    torch.cuda.synchronize()
+    el_full = time.perf_counter() - t0
+    runs = {}
+    for name, mode in (("learned", 0), ("all_linear", -1)):
+        ul = snap.clone()
+        ctx.set_router(theta, thr, mode)
+        fb0 = ctx.router_stats()[2]
+        fracs = []
+        failed = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nsteps):
+            try:
+                ctx.cfl_dt(ul)
+                ctx.step(ul, dts[i])
+            except wombat.WenoError as e:
+                failed = f"step {i + 1}: {e}"
+                break
+            sm, tot, _ = ctx.router_stats()       # smooth share of the step's last stage
+            fracs.append(sm / tot)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if failed:
+            runs[name] = {"failed": failed}
+            print(f"[bench] learned: route {name} failed at {failed}", file=sys.stderr, flush=True)
+            del ul
+            continue
+        fb = ctx.router_stats()[2] - fb0
+        l1, linf = rel_errors(ul, u, sl)
+        runs[name] = {"value": n ** 3 * 4 * nsteps / el, "ms_per_step": el / nsteps * 1e3,
+                      "speedup_vs_full_fp32": el_full / el, "l1_rel_vs_full_max_var": l1,
+                      "linf_rel_vs_full_max_var": linf, "smooth_fraction_mean": sum(fracs) / len(fracs),
+                      "full_weno_fallback_steps": fb}
+        print(f"[bench] learned: route {name}: {el / nsteps * 1e3:.1f} ms/step (full {el_full / nsteps * 1e3:.1f}), "
+              f"L1 {l1:.2e}, smooth {sum(fracs) / len(fracs):.3f}, fallbacks {fb}", file=sys.stderr, flush=True)
+        del ul
+    ctx.set_router(None, 0.5, 0)
+    res = {"value": runs["learned"].get("value"), "unit": "zone-stage updates/s", "dtype": "f32 + bf16 MLP",
+           "workload": f"shocked turbulence {n}^3, rms Mach 3, beta 10, 10 % compressive, log-normal "
+                       f"rho sigma 0.5; {a.pre_steps} full-WENO FP32 steps, then {nsteps} steps per route",
+           "full_fp32": {"value": n ** 3 * 4 * nsteps / el_full, "ms_per_step": el_full / nsteps * 1e3},
+           "learned": runs["learned"], "all_linear_no_network": runs["all_linear"],
+           "router": {"threshold": thr, "label": f"flux excess > {router.LABEL_THRESHOLD:g}",
+                      "train_interfaces": int(9 * nval), "train_pre_steps": pre_tr,
+                      "train_steps": a.train_steps, "train_seconds": train_s,
+                      "loss_first_last": [hist[0][1], hist[-1][1]],
+                      "heldout_train_recipe": val, "eval_snapshot": ev}}
+    del ctx, u, snap
     return res
 
 
@@ -240,6 +382,10 @@ def main():
 
     if a.batch_patches > 0:
         out.setdefault("forms", {})["batched_fp32"] = batched_form(a, wombat, inputs, opcount)
+        torch.cuda.empty_cache()
+    if not a.no_learned:
+        from paper_1808_10633_amd import router
+        out.setdefault("forms", {})["learned_fp32"] = learned_form(a, wombat, inputs, router)
         torch.cuda.empty_cache()
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

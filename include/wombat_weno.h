@@ -252,6 +252,88 @@ int wombat_weno_batch_shape(const wombat_weno_batch_t *b, int *ft, int *blocks_p
 int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, const char *cache_path,
                                double *best_ms);
 
+/* ------------------------------------------------------------------------
+ * Learned troubled-interface router.  Not part of the paper's method: a
+ * small MLP decides per interface whether the characteristic WENO flux of
+ * Sec. 2.1 is needed; interfaces it calls smooth get the linear fifth-order
+ * component-wise flux (one Lax-Friedrichs speed max(|v_n| + c_f) over the
+ * stencil, weights (2,-13,47,27,-3)/60 on F^+ and the mirror on F^-).
+ *
+ * MLP: 48 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid).  Inputs: the six cells
+ * i-2..i+3 of the interface, 8 conserved variables each in the sweep frame
+ * (rho, m_n, m_t1, m_t2, B_n, B_t1, B_t2, E), each variable normalised over
+ * the stencil as (q - mean)/(max|q - mean| + 1e-5 max|q| + 1e-30), ordered
+ * x[v*6 + j].
+ * Parameters: one FP32 device vector of wombat_mlp_param_count() = 2657
+ * values: W1 (32x48 row-major [out][in]), b1 (32), W2 (32x32), b2 (32),
+ * w3 (32), b3.  Products run in BF16 on MFMA with FP32 accumulation.
+ * Training label ("troubled"): the flux excess below exceeds a threshold
+ * (1e-4 by default in the Python training code).
+ * ------------------------------------------------------------------------ */
+
+/* Route the sweeps of an FP32 context through the router: d_theta
+ * (device, caller-owned, must stay valid while set; NULL switches the
+ * router off), threshold in (0,1): an interface is troubled when
+ * sigmoid(logit) > threshold (NaN counts as troubled).  mode 0 routes; +1
+ * sends every interface to the full flux and -1 every one to the linear
+ * flux (through the same kernel).  The first call with a non-NULL d_theta
+ * allocates one state-sized backup array (kept until destroy).
+ * Full WENO is the fallback: wombat_weno_step with mode 0 keeps u^n in that
+ * array, and if the routed step leaves a non-physical cell it is redone
+ * from u^n with full characteristic WENO on every interface (counted in
+ * router_stats).  Stages and rhs calls have no fallback.
+ * WW_ERR_UNSUPPORTED on FP64 contexts, WW_ERR_INVALID_ARG for a threshold
+ * or mode out of range, WW_ERR_OOM if the backup cannot be allocated. */
+int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double threshold, int mode);
+
+/* Interfaces routed to the linear flux by the three sweeps of the last
+ * right-hand side or stage, the number of interfaces swept, and (if
+ * fallbacks is not NULL) how many routed steps were redone with full WENO
+ * since init.  Synchronous. */
+int wombat_weno_router_stats(wombat_weno_t *ctx, int64_t *smooth, int64_t *total, int64_t *fallbacks);
+
+/* Training data: for n interfaces d_where[s] = (dir, i, j, k) (device,
+ * int32 x 4; the coordinate along dir is a face index 0..n_dir, the others
+ * interior cell indices) of the state d_u (its ghosts are filled first),
+ * write (all device FP32, caller-owned, none NULL):
+ *   d_X[s*48..]   the 48 features;
+ *   d_dev[s]      the largest deviation of any weight of eq. (3) (any
+ *                 field, either side of eq. (1)) from (0.1, 0.6, 0.3);
+ *   d_excess[s]   the flux excess max_c |Fc_full - Fc_lin| / (a S_c): the
+ *                 characteristic flux against the linear flux, with a the
+ *                 largest |v_n| + c_f on the stencil and S = max rho (mass),
+ *                 max(|m| + rho a) (momenta), max(|B| + sqrt(rho) a)
+ *                 (fields), max E (energy) over the stencil.
+ * A position outside the box (dir not an active axis, a face index outside
+ * 0..n_dir, a transverse index outside 0..n-1) gets NaN in all three
+ * outputs; the others are unaffected.  WW_ERR_INVALID_ARG for NULL
+ * pointers or n < 1.  Asynchronous. */
+int wombat_weno_router_sample(wombat_weno_t *ctx, void *d_u, const int32_t *d_where, int n,
+                              float *d_X, float *d_dev, float *d_excess);
+
+/* Number of MLP parameters (2657). */
+int wombat_mlp_param_count(void);
+
+/* Logits of n samples d_X[n][48] into d_logit[n] (device FP32), on stream
+ * (hipStream_t, NULL = null stream).  Asynchronous. */
+int wombat_mlp_forward(void *stream, const float *d_theta, const float *d_X, int n, float *d_logit);
+
+/* Workspace (in floats) wombat_mlp_grad needs for n samples. */
+int64_t wombat_mlp_grad_workspace(int n);
+
+/* Gradient of the mean binary cross-entropy of sigmoid(logit) against
+ * targets d_t[n] over the n samples: d_grad[2657] and, if d_loss is not
+ * NULL, the loss.  d_work: wombat_mlp_grad_workspace(n) floats.  The sum
+ * over samples runs in a fixed order (deterministic).  Asynchronous. */
+int wombat_mlp_grad(void *stream, const float *d_theta, const float *d_X, const float *d_t, int n,
+                    float *d_work, float *d_grad, float *d_loss);
+
+/* One Adam step (step >= 1 counts from 1) on the FP32 master parameters
+ * with moment vectors d_m, d_v (2657 each, zero before the first step).
+ * Asynchronous. */
+int wombat_mlp_adam(void *stream, float *d_theta, float *d_m, float *d_v, const float *d_grad,
+                    int step, float lr, float beta1, float beta2, float eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -108,6 +108,8 @@ def lib():
         L.orc_rhs.restype = C.c_int
         L.orc_rhs_nofill.argtypes = [g, _dp, _dp]
         L.orc_rhs_nofill.restype = C.c_int
+        L.orc_rhs_linear.argtypes = [g, _dp, _dp]
+        L.orc_rhs_linear.restype = C.c_int
         L.orc_cfl_dt.argtypes = [g, _dp]
         L.orc_cfl_dt.restype = d
         L.orc_rk4_step.argtypes = [g, _dp, d]
@@ -194,6 +196,31 @@ def linear_flux(Us, gamma=5.0 / 3.0):
 
 
 # ---- grid operations ----
+def flux_excess(Us, gamma=5.0 / 3.0, eps=1e-6):
+    """Training label of the learned router (not part of the paper): how far
+    the characteristic WENO flux of Sec. 2.1 departs from the linear
+    fifth-order component-wise flux at one interface, per component relative
+    to a stencil scale, maximised over the components:
+
+      r = max_c |Fhat_c - Flin_c| / (a S_c),  a = max_j (|v_n| + c_f),
+      S = max rho (mass), max (|m| + rho a) (momenta), max (|B| + sqrt(rho) a)
+          (fields), max E (energy), maxima over the six stencil cells.
+    """
+    Us = np.asarray(Us, dtype=np.float64)
+    Ff = interface_flux(Us, gamma, eps)
+    Fl = linear_flux(Us, gamma)
+    a = 0.0
+    for j in range(6):
+        cf = wave_speeds(Us[j], 0, gamma)[0]
+        a = max(a, abs(Us[j, 1] / Us[j, 0]) + cf)
+    rho = Us[:, 0]
+    m = np.sqrt((Us[:, 1:4] ** 2).sum(1))
+    b = np.sqrt((Us[:, 4:7] ** 2).sum(1))
+    S = np.array([rho.max(), (m + rho * a).max(), (m + rho * a).max(), (m + rho * a).max(), np.inf,
+                  (b + np.sqrt(rho) * a).max(), (b + np.sqrt(rho) * a).max(), Us[:, 7].max()])
+    return float((np.abs(Ff - Fl) / (a * S)).max())
+
+
 def _state(grid: Grid, u):
     if u.shape != grid.shape or u.dtype != np.float64 or not u.flags.c_contiguous:
         raise ValueError(f"state must be C-contiguous float64 {grid.shape}, got {u.shape} {u.dtype}")
@@ -220,6 +247,16 @@ def rhs_nofill(grid: Grid, u):
     g = grid.c()
     out = np.zeros(grid.shape)
     rc = lib().orc_rhs_nofill(C.byref(g), _state(grid, u).reshape(-1), out.reshape(-1))
+    if rc != 0:
+        raise FloatingPointError("oracle rhs: non-physical state")
+    return out
+
+
+def rhs_linear(grid: Grid, u):
+    """L(U) with the linear component-wise flux at every interface."""
+    g = grid.c()
+    out = np.zeros(grid.shape)
+    rc = lib().orc_rhs_linear(C.byref(g), _state(grid, u).reshape(-1), out.reshape(-1))
     if rc != 0:
         raise FloatingPointError("oracle rhs: non-physical state")
     return out

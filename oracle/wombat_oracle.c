@@ -570,7 +570,7 @@ static int nonphysical(const double U[8], double gamma)
 
 /* L(U): the semi-discrete right-hand side of one Runge-Kutta stage.
  * Returns 0, or -1 if a stencil cell is non-physical (rho<=0 or p<=0). */
-static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fill)
+static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fill, int linear)
 {
     geom G = mkgeom(gr);
     long ntot = 8 * G.sv;
@@ -612,7 +612,8 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
                 for (c = 0; c < 8; ++c) Us[8 * j + c] = u[perm[c] * G.sv + id];
                 if (nonphysical(Us + 8 * j, gr->gamma)) bad = 1;
             }
-            orc_interface_flux(Us, gr->gamma, gr->eps, Fh);
+            if (linear) orc_linear_flux(Us, gr->gamma, Fh);
+            else orc_interface_flux(Us, gr->gamma, gr->eps, Fh);
             long fi = fidx(&FF[d], pos[0], pos[1], pos[2]);
             for (c = 0; c < 8; ++c) FF[d].f[perm[c] * FF[d].total + fi] = Fh[c];
         }
@@ -659,14 +660,20 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
 
 int orc_rhs(const orc_grid *gr, const double *u, double *dudt)
 {
-    return rhs_impl(gr, u, dudt, 1);
+    return rhs_impl(gr, u, dudt, 1, 0);
 }
 
 /* As orc_rhs, but the ghost zones of u are used as given (not refilled):
  * L at a cell of a block cut out of a larger state with its ghosts. */
 int orc_rhs_nofill(const orc_grid *gr, const double *u, double *dudt)
 {
-    return rhs_impl(gr, u, dudt, 0);
+    return rhs_impl(gr, u, dudt, 0, 0);
+}
+
+/* As orc_rhs with the linear component-wise flux at every interface. */
+int orc_rhs_linear(const orc_grid *gr, const double *u, double *dudt)
+{
+    return rhs_impl(gr, u, dudt, 1, 1);
 }
 
 /* dt = C / max over interior cells of sum_d (|v_d| + c_f,d) / dx_d.

@@ -73,6 +73,7 @@ long   orc_state_size(const orc_grid *g);          /* doubles in one state */
 void   orc_fill_ghosts(const orc_grid *g, double *u);
 int    orc_rhs(const orc_grid *g, const double *u, double *dudt);
 int    orc_rhs_nofill(const orc_grid *g, const double *u, double *dudt);
+int    orc_rhs_linear(const orc_grid *g, const double *u, double *dudt);
 double orc_cfl_dt(const orc_grid *g, const double *u);
 int    orc_rk4_step(const orc_grid *g, double *u, double dt);
 void   orc_sums(const orc_grid *g, const double *u, double out[8]);

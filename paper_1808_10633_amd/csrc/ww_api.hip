@@ -3,6 +3,7 @@
 // enqueued on the context's stream; no allocation happens after init.
 #include "../../include/wombat_weno.h"
 #include "ww_internal.h"
+#include "ww_router.h"
 
 #include <cmath>
 #include <cstdio>
@@ -29,6 +30,13 @@ struct wombat_weno {
     double *hsmall;        // pinned host mirror of dsmall (16 doubles + flag)
     int nblk;
     hipEvent_t ev[2];      // kernel timing
+    const float *router;   // learned-router parameters (caller-owned), or NULL
+    float router_thr;      // logit threshold of "troubled"
+    int router_force;      // 0 routed, +1 all full WENO, -1 all linear (same kernel)
+    int32_t *nsmooth;      // per-block smooth counts of the last learned sweeps
+    long nsm_blocks[3];
+    void *backup;          // u at the start of a routed step (allocated with the router)
+    int64_t fallbacks;     // routed steps redone with full WENO
     hipStream_t st;
     int sticky;            // a HIP error happened: every later call fails
     std::string err;
@@ -166,6 +174,8 @@ void release(wombat_weno_t *c)
     if (c->partflag) (void)hipFree(c->partflag);
     if (c->dsmall) (void)hipFree(c->dsmall);
     if (c->hsmall) (void)hipHostFree(c->hsmall);
+    if (c->nsmooth) (void)hipFree(c->nsmooth);
+    if (c->backup) (void)hipFree(c->backup);
     for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
@@ -206,6 +216,16 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
     for (int d = 0; d < 3; ++d) {
         if (!c->G.act[d]) continue;
+        if constexpr (sizeof(T) == 4) {
+            if (c->router) {
+                int32_t *ns = c->nsmooth;
+                for (int e = 0; e < d; ++e) ns += c->nsm_blocks[e];
+                WW_CHECK(c, ww::launch_learned_sweep(d, (const float *)us, (float *)c->ff[d], c->G, c->F[d], P,
+                                                     c->router, c->router_thr, c->router_force, ns,
+                                                     c->st));
+                continue;
+            }
+        }
         WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->st));
     }
     WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, (const T *)c->ff[0],
@@ -326,6 +346,15 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
         c->hsmall = nullptr;
         return oom("pinned host buffer");
     }
+    if (cfg->precision == WW_FP32_MIXED) {
+        long tot = 0;
+        for (int d = 0; d < 3; ++d) {
+            c->nsm_blocks[d] = c->G.act[d] ? ww::learned_sweep_blocks(d, c->F[d]) : 0;
+            tot += c->nsm_blocks[d];
+        }
+        if (dev_alloc((void **)&c->nsmooth, sizeof(int32_t) * (tot > 0 ? tot : 1)) != hipSuccess)
+            return oom("router counters");
+    }
     for (int i = 0; i < 2; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
             c->ev[i] = nullptr;
@@ -371,26 +400,43 @@ int wombat_weno_cfl_dt_device(wombat_weno_t *ctx, const void *d_u, double *d_dt,
     return cfl_device_t<float>(ctx, (const float *)d_u, d_dt, d_flag);
 }
 
+namespace {
+
+// CFL step and number of non-physical cells of d_u (synchronous).
+int cfl_and_count(wombat_weno_t *ctx, const void *d_u, double *dt, int32_t *bad)
+{
+    int rc = ctx->cfg.precision == WW_FP64
+                 ? cfl_device_t<double>(ctx, (const double *)d_u, ctx->dsmall, ctx->dflag)
+                 : cfl_device_t<float>(ctx, (const float *)d_u, ctx->dsmall, ctx->dflag);
+    if (rc) return rc;
+    WW_CHECK(ctx, hipMemcpyAsync(ctx->hsmall, ctx->dsmall, sizeof(double) * 20,
+                                 hipMemcpyDeviceToHost, ctx->st));
+    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
+    *bad = *(int32_t *)(ctx->hsmall + 16);
+    *dt = ctx->hsmall[0];
+    return WW_OK;
+}
+
+int nonphysical(wombat_weno_t *ctx, int32_t bad)
+{
+    char buf[96];
+    snprintf(buf, sizeof buf, "%d non-physical cells (rho<=0, p<=0 or non-finite)", (int)bad);
+    return fail_ctx(ctx, WW_ERR_NONPHYSICAL, buf);
+}
+
+}  // namespace
+
 int wombat_weno_cfl_dt(wombat_weno_t *ctx, const void *d_u, double *dt)
 {
     int rc = precheck(ctx);
     if (rc) return rc;
     if (!d_u || !dt) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
     DevGuard dg(ctx->cfg.device);
-    rc = ctx->cfg.precision == WW_FP64
-             ? cfl_device_t<double>(ctx, (const double *)d_u, ctx->dsmall, ctx->dflag)
-             : cfl_device_t<float>(ctx, (const float *)d_u, ctx->dsmall, ctx->dflag);
-    if (rc) return rc;
-    WW_CHECK(ctx, hipMemcpyAsync(ctx->hsmall, ctx->dsmall, sizeof(double) * 20,
-                                 hipMemcpyDeviceToHost, ctx->st));
-    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
-    int32_t flag = *(int32_t *)(ctx->hsmall + 16);
-    if (flag) {
-        char buf[96];
-        snprintf(buf, sizeof buf, "%d non-physical cells (rho<=0, p<=0 or non-finite)", (int)flag);
-        return fail_ctx(ctx, WW_ERR_NONPHYSICAL, buf);
-    }
-    *dt = ctx->hsmall[0];
+    int32_t bad = 0;
+    double d = 0.0;
+    if ((rc = cfl_and_count(ctx, d_u, &d, &bad))) return rc;
+    if (bad) return nonphysical(ctx, bad);
+    *dt = d;
     return WW_OK;
 }
 
@@ -430,6 +476,20 @@ int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0, vo
                              (float *)d_acc, (float *)d_us_out, k);
 }
 
+namespace {
+
+int rk4_stages(wombat_weno_t *ctx, void *d_u, double dt)
+{
+    void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
+    int rc;
+    if ((rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A))) return rc;
+    if ((rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, B))) return rc;
+    if ((rc = wombat_weno_stage(ctx, 2, dt, d_u, B, acc, A))) return rc;
+    return wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u);
+}
+
+}  // namespace
+
 int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used)
 {
     int rc = precheck(ctx);
@@ -440,11 +500,30 @@ int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used)
         rc = wombat_weno_cfl_dt(ctx, d_u, &dt);
         if (rc) return rc;
     }
-    void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
-    if ((rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A))) return rc;
-    if ((rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, B))) return rc;
-    if ((rc = wombat_weno_stage(ctx, 2, dt, d_u, B, acc, A))) return rc;
-    if ((rc = wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u))) return rc;
+    // a routed step keeps u^n; if it leaves a non-physical cell the step is
+    // redone from u^n with full characteristic WENO everywhere
+    const bool guard = ctx->router && ctx->router_force == 0;
+    if (guard) {
+        DevGuard dg(ctx->cfg.device);
+        WW_CHECK(ctx, hipMemcpyAsync(ctx->backup, d_u, ctx->elems * ctx->esize, hipMemcpyDeviceToDevice,
+                                     ctx->st));
+    }
+    if ((rc = rk4_stages(ctx, d_u, dt))) return rc;
+    if (guard) {
+        DevGuard dg(ctx->cfg.device);
+        int32_t bad = 0;
+        double unused;
+        if ((rc = cfl_and_count(ctx, d_u, &unused, &bad))) return rc;
+        if (bad) {
+            WW_CHECK(ctx, hipMemcpyAsync(d_u, ctx->backup, ctx->elems * ctx->esize,
+                                         hipMemcpyDeviceToDevice, ctx->st));
+            ctx->router_force = 1;
+            rc = rk4_stages(ctx, d_u, dt);
+            ctx->router_force = 0;
+            if (rc) return rc;
+            ++ctx->fallbacks;
+        }
+    }
     if (dt_used) *dt_used = dt;
     return WW_OK;
 }
@@ -499,5 +578,103 @@ int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[
     if (ctx->cfg.precision == WW_FP64) return time_kernels_t<double>(ctx, (double *)d_u, reps, ms);
     return time_kernels_t<float>(ctx, (float *)d_u, reps, ms);
 }
+
+int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double threshold, int mode)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (ctx->cfg.precision != WW_FP32_MIXED)
+        return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs on FP32 contexts");
+    if (!d_theta) { ctx->router = nullptr; return WW_OK; }
+    if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
+    if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");
+    if (!ctx->backup) {
+        DevGuard dg(ctx->cfg.device);
+        if (dev_alloc(&ctx->backup, ctx->elems * ctx->esize) != hipSuccess) {
+            ctx->backup = nullptr;
+            (void)hipGetLastError();
+            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the routed-step backup");
+        }
+    }
+    ctx->router = d_theta;
+    ctx->router_thr = (float)std::log(threshold / (1.0 - threshold));
+    ctx->router_force = mode;
+    return WW_OK;
+}
+
+int wombat_weno_router_stats(wombat_weno_t *ctx, int64_t *smooth, int64_t *total, int64_t *fallbacks)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!smooth || !total) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
+    if (!ctx->nsmooth) return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "no router counters (FP64 context)");
+    DevGuard dg(ctx->cfg.device);
+    long tot = ctx->nsm_blocks[0] + ctx->nsm_blocks[1] + ctx->nsm_blocks[2];
+    std::string buf;
+    int32_t *h = nullptr;
+    WW_CHECK(ctx, hipStreamSynchronize(ctx->st));
+    h = (int32_t *)malloc(sizeof(int32_t) * (tot > 0 ? tot : 1));
+    if (!h) return fail_ctx(ctx, WW_ERR_OOM, "host allocation failed");
+    hipError_t e = hipMemcpy(h, ctx->nsmooth, sizeof(int32_t) * tot, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { free(h); return hip_fail(ctx, e, "hipMemcpy router counters"); }
+    int64_t s = 0;
+    for (long i = 0; i < tot; ++i) s += h[i];
+    free(h);
+    int64_t faces = 0;
+    for (int d = 0; d < 3; ++d) if (ctx->G.act[d]) faces += ctx->F[d].sc;
+    *smooth = s;
+    *total = faces;
+    if (fallbacks) *fallbacks = ctx->fallbacks;
+    return WW_OK;
+}
+
+int wombat_weno_router_sample(wombat_weno_t *ctx, void *d_u, const int32_t *d_where, int n,
+                              float *d_X, float *d_dev, float *d_excess)
+{
+    int rc = precheck(ctx);
+    if (rc) return rc;
+    if (!d_u || !d_where || !d_X || !d_dev || !d_excess || n < 1)
+        return fail_ctx(ctx, WW_ERR_INVALID_ARG, "bad argument");
+    if ((rc = wombat_weno_fill_ghosts(ctx, d_u))) return rc;
+    DevGuard dg(ctx->cfg.device);
+    ww::Phys P{ ctx->cfg.gamma, ctx->cfg.eps, 1.0 / (ctx->cfg.gamma - 1.0) };
+    if (ctx->cfg.precision == WW_FP64)
+        WW_CHECK(ctx, ww::launch_router_sample<double>((const double *)d_u, ctx->G, P, d_where, n, d_X, d_dev, d_excess, ctx->st));
+    else
+        WW_CHECK(ctx, ww::launch_router_sample<float>((const float *)d_u, ctx->G, P, d_where, n, d_X, d_dev, d_excess, ctx->st));
+    return WW_OK;
+}
+
+int wombat_mlp_forward(void *stream, const float *d_theta, const float *d_X, int n, float *d_logit)
+{
+    if (!d_theta || !d_X || !d_logit || n < 1) return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = ww::launch_mlp_infer(d_theta, d_X, n, d_logit, (hipStream_t)stream);
+    return e == hipSuccess ? WW_OK : hip_fail(nullptr, e, "mlp forward");
+}
+
+int64_t wombat_mlp_grad_workspace(int n)
+{
+    return n < 1 ? -1 : (int64_t)ww::mlp_grad_blocks(n) * (ww::NPARAM + 1);
+}
+
+int wombat_mlp_grad(void *stream, const float *d_theta, const float *d_X, const float *d_t, int n,
+                    float *d_work, float *d_grad, float *d_loss)
+{
+    if (!d_theta || !d_X || !d_t || !d_work || !d_grad || n < 1)
+        return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = ww::launch_mlp_grad(d_theta, d_X, d_t, n, d_work, d_grad, d_loss, (hipStream_t)stream);
+    return e == hipSuccess ? WW_OK : hip_fail(nullptr, e, "mlp grad");
+}
+
+int wombat_mlp_adam(void *stream, float *d_theta, float *d_m, float *d_v, const float *d_grad,
+                    int step, float lr, float beta1, float beta2, float eps)
+{
+    if (!d_theta || !d_m || !d_v || !d_grad || step < 1 || !(lr > 0.f))
+        return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "bad argument");
+    hipError_t e = ww::launch_mlp_adam(d_theta, d_m, d_v, d_grad, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    return e == hipSuccess ? WW_OK : hip_fail(nullptr, e, "mlp adam");
+}
+
+int wombat_mlp_param_count(void) { return ww::NPARAM; }
 
 }  // extern "C"

@@ -61,8 +61,8 @@ __device__ __forceinline__ float frcp(float x)
 }
 
 // phi_N of eq. (2) with the weights of eqs. (3)-(7).  e4 = epsilon / 4.
-template <typename T>
-__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4)
+template <typename T, bool LBL = false>
+__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
 {
     // Smoothness indicators of eqs. (5)-(7), expanded into the quadratic forms
     // IS_0 = 16a^2 - 44ab + 40b^2, IS_1 = 16b^2 - 20bc + 16c^2,
@@ -73,11 +73,24 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4)
     T q0 = fma(a, fma(T(4), a, T(-11) * b), fma(T(10), b2, e4));
     T q1 = fma(T(4), b2 + c2, fma(T(-5), b * c, e4));
     T q2 = fma(d, fma(T(4), d, T(-11) * c), fma(T(10), c2, e4));
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the products of four (epsilon + IS)/4 below overflow once IS
+        // passes ~5e9 (strong blasts); scaled by their largest they stay in
+        // (0, 1], and the weights, which depend only on ratios, are unchanged
+        const T s = frcp(fmax(q0, fmax(q1, q2)));
+        q0 *= s; q1 *= s; q2 *= s;
+    }
     q0 *= q0; q1 *= q1; q2 *= q2;
     // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
     // written over the common denominator q0 q1 q2 (one reciprocal).
     T n0 = q1 * q2, n1 = T(6) * q0 * q2, n2 = T(3) * q0 * q1;
     T inv = frcp(n0 + n1 + n2);
+    if constexpr (LBL) {
+        // largest deviation of (omega_0, omega_1, omega_2) from (0.1, 0.6, 0.3)
+        T w0 = n0 * inv, w1 = n1 * inv, w2 = n2 * inv;
+        T dv = fmax(fmax(fabs(w0 - T(0.1)), fabs(w1 - T(0.6))), fabs(w2 - T(0.3)));
+        *dev = fmax(*dev, dv);
+    }
     // eq. (2): omega_0 (a-2b+c)/3 + (omega_2 - 1/2)(b-2c+d)/6
     T x3 = (a - T(2) * b + c) * T(1.0 / 3.0);
     T y6 = (b - T(2) * c + d) * T(1.0 / 6.0);
@@ -87,8 +100,9 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4)
 // eq. (1) for one field.  cc: projected central term; df, du: projected flux
 // and state differences (k = 0..4 at i-3/2 .. i+5/2), both already carrying
 // the 1/2 of the Lax-Friedrichs split; al: LF speed.
-template <typename T>
-__device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps)
+template <typename T, bool LBL = false>
+__device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps,
+                                        T *dev = nullptr)
 {
     T dp[5], dm[5];
 #pragma unroll
@@ -96,7 +110,8 @@ __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5]
         dp[k] = fma(al, du[k], df[k]);
         dm[k] = fma(-al, du[k], df[k]);
     }
-    return cc - phi_n(dp[0], dp[1], dp[2], dp[3], eps) + phi_n(dm[4], dm[3], dm[2], dm[1], eps);
+    return cc - phi_n<T, LBL>(dp[0], dp[1], dp[2], dp[3], eps, dev)
+              + phi_n<T, LBL>(dm[4], dm[3], dm[2], dm[1], eps, dev);
 }
 
 // Stage one cell: sweep-frame conserved variables and derived quantities.
@@ -132,9 +147,12 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
 // quantities, off: offset of cell i-2, cstr: stride between cells.
 // out: sweep-frame flux (rho, mn, mt1, mt2, Bt1, Bt2, E).
-template <typename T>
+// LBL: also return in *dev the largest deviation of any weight of any field
+// from the linear weights (the label of a troubled interface).
+template <typename T, bool LBL = false>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
-                                          double gamma, double igm1, T eps, T (&out)[7])
+                                          double gamma, double igm1, T eps, T (&out)[7],
+                                          T *dev = nullptr)
 {
 #define QQ(q, j) sq[(q) * qs + off + (j) * cstr]
     T C[7], dY[5][7], dZ[5][7], am[7];
@@ -250,10 +268,10 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         T df[5], du[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] + odf[k]; du[k] = edu[k] + odu[k]; }
-        T fplus = weno_field(ec + oc, df, du, am[hi], teps);
+        T fplus = weno_field<T, LBL>(ec + oc, df, du, am[hi], teps, dev);
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] - odf[k]; du[k] = edu[k] - odu[k]; }
-        T fminus = weno_field(ec - oc, df, du, am[lo], teps);
+        T fminus = weno_field<T, LBL>(ec - oc, df, du, am[lo], teps, dev);
         S = fplus + fminus;
         D = fplus - fminus;
     };
@@ -287,7 +305,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
             df[k] = kh * (dY[k][0] - ke6 * dY[k][6]);
             du[k] = kh * (dZ[k][0] - ke6 * dZ[k][6]);
         }
-        G[0] += weno_field(cc, df, du, am[3], teps);
+        G[0] += weno_field<T, LBL>(cc, df, du, am[3], teps, dev);
     }
 
     // back to (vt1, vt2), (Bt1, Bt2) and through dU/dW
@@ -302,6 +320,105 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     out[5] = gb2;
     out[6] = th * G[0] + trb * (tv * G[1] + t1 * gv1 + t2 * gv2) + tb1 * gb1 + tb2 * gb2
            + G[6] * T(igm1);
+}
+
+// Linear fifth-order component-wise flux of the six staged cells (the cheap
+// flux of interfaces the learned router calls smooth): one Lax-Friedrichs
+// speed alpha = max(|v_n| + c_f) over the stencil for every component and
+// the linear-weight form of eq. (1), (2,-13,47,27,-3)/60 on F^+ and the
+// mirror (-3,27,47,-13,2)/60 on F^-.
+template <typename T>
+__device__ __forceinline__ void linear_flux(const T *__restrict__ sq, int qs, int off, int cstr,
+                                            T (&out)[7])
+{
+#define QL(q, j) sq[(q) * qs + off + (j) * cstr]
+    T F[6][7], U[6][7], al = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        T r = QL(0, j), mn = QL(1, j), m1 = QL(2, j), m2 = QL(3, j);
+        T bn = QL(4, j), b1 = QL(5, j), b2 = QL(6, j), e = QL(7, j);
+        T p = QL(8, j), ir = QL(9, j), cf = QL(10, j);
+        T vn = mn * ir, v1 = m1 * ir, v2 = m2 * ir;
+        T pt = p + T(0.5) * (bn * bn + b1 * b1 + b2 * b2);
+        F[j][0] = mn; F[j][1] = mn * vn + pt - bn * bn; F[j][2] = m1 * vn - bn * b1;
+        F[j][3] = m2 * vn - bn * b2; F[j][4] = vn * b1 - v1 * bn; F[j][5] = vn * b2 - v2 * bn;
+        F[j][6] = (e + pt) * vn - bn * (vn * bn + v1 * b1 + v2 * b2);
+        U[j][0] = r; U[j][1] = mn; U[j][2] = m1; U[j][3] = m2; U[j][4] = b1; U[j][5] = b2; U[j][6] = e;
+        al = fmax(al, fabs(vn) + cf);
+    }
+#undef QL
+    const T h = T(0.5) * al;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        T pp[6], mm[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            pp[j] = fma(h, U[j][c], T(0.5) * F[j][c]);
+            mm[j] = fma(-h, U[j][c], T(0.5) * F[j][c]);
+        }
+        out[c] = (T(2) * pp[0] - T(13) * pp[1] + T(47) * pp[2] + T(27) * pp[3] - T(3) * pp[4]
+                  - T(3) * mm[1] + T(27) * mm[2] + T(47) * mm[3] - T(13) * mm[4] + T(2) * mm[5])
+                 * T(1.0 / 60.0);
+    }
+}
+
+// Router features of one interface from its six staged cells (i-2..i+3),
+// six per sweep-frame conserved variable v, stored x[v*6 + j], all of the
+// form L(y) = 1 + log10(y / S_v + 1e-8) / 4:
+//   j = 0  largest first difference max |q_{m+1} - q_m|;
+//   j = 1  the jump across the interface |q_3 - q_2|;
+//   j = 2..5  largest |second|, |third|, |fourth| and the |fifth| difference.
+// The scales are those of the flux-excess label: with a = max(|v_n| + c_f)
+// on the stencil, S = max rho (mass), max(|m| + rho a) (momenta),
+// max(|B| + sqrt(rho) a) (fields), max E (energy).  On smooth data the
+// m-th difference falls like (kh)^m, so smoothness and amplitude are both
+// differences of O(1) features, which BF16 carries; the raw stencil values
+// would need ~20 bits to show a fifth difference.
+template <typename T>
+__device__ __forceinline__ void router_features(const T *__restrict__ sq, int qs, int off, int cstr,
+                                                float (&x)[48])
+{
+#define QF(q, j) sq[(q) * qs + off + (j) * cstr]
+    T a = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a = fmax(a, fabs(QF(1, j) * QF(9, j)) + QF(10, j));
+    T sr = T(0), sm = T(0), sb = T(0), se = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const T r = QF(0, j);
+        const T m = sqrt(QF(1, j) * QF(1, j) + QF(2, j) * QF(2, j) + QF(3, j) * QF(3, j));
+        const T b = sqrt(QF(4, j) * QF(4, j) + QF(5, j) * QF(5, j) + QF(6, j) * QF(6, j));
+        sr = fmax(sr, r);
+        sm = fmax(sm, m + r * a);
+        sb = fmax(sb, b + sqrt(r) * a);
+        se = fmax(se, QF(7, j));
+    }
+    const T isr = T(1) / sr, ism = T(1) / sm, isb = T(1) / sb, ise = T(1) / se;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const T is = v == 0 ? isr : v < 4 ? ism : v < 7 ? isb : ise;
+        T d[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) d[j] = QF(v, j);
+        T y[6];
+        y[1] = fabs(d[3] - d[2]);
+#pragma unroll
+        for (int m = 1; m <= 5; ++m) {           // d <- its next difference
+            T mx = T(0);
+#pragma unroll
+            for (int j = 0; j + m < 6; ++j) { d[j] = d[j + 1] - d[j]; mx = fmax(mx, fabs(d[j])); }
+            y[m == 1 ? 0 : m] = mx;
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const T z = y[j] * is + T(1e-8);
+            if constexpr (sizeof(T) == 4)
+                x[v * 6 + j] = 1.0f + 0.0752574989f * __log2f(z);          // log10(2) / 4
+            else
+                x[v * 6 + j] = (float)(T(1) + T(0.25) * log10(z));
+        }
+    }
+#undef QF
 }
 
 // Store a sweep-frame interface flux in grid components:

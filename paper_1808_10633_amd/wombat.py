@@ -90,6 +90,16 @@ def lib():
         L.wombat_weno_batch_dt.argtypes = [vp, vp, vp]
         L.wombat_weno_batch_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.wombat_weno_batch_autotune.argtypes = [vp, vp, C.c_char_p, C.POINTER(d)]
+        L.wombat_weno_set_router.argtypes = [vp, vp, d, i32]
+        L.wombat_weno_router_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                               C.POINTER(C.c_int64)]
+        L.wombat_weno_router_sample.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.wombat_mlp_param_count.restype = i32
+        L.wombat_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+        L.wombat_mlp_grad_workspace.argtypes = [i32]
+        L.wombat_mlp_grad_workspace.restype = C.c_int64
+        L.wombat_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+        L.wombat_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float]
         _lib = L
     return _lib
 
@@ -206,6 +216,34 @@ class Context:
         _check(lib().wombat_weno_time_kernels(self.h, self._ptr(u, "u"), int(reps), out), self.h)
         return list(out)
 
+    def set_router(self, theta, threshold=0.5, mode=0):
+        """Learned routing of the sweeps (FP32 contexts); theta=None switches it off."""
+        self._theta = theta
+        ptr = None if theta is None else C.c_void_p(theta.data_ptr())
+        _check(lib().wombat_weno_set_router(self.h, ptr, float(threshold), int(mode)), self.h)
+
+    def router_stats(self):
+        """(interfaces routed smooth in the last rhs/stage, interfaces swept,
+        routed steps redone with full WENO since init)."""
+        s, t, f = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().wombat_weno_router_stats(self.h, C.byref(s), C.byref(t), C.byref(f)), self.h)
+        return s.value, t.value, f.value
+
+    def router_sample(self, u, where):
+        """where: int32 cuda tensor (n, 4) of (dir, i, j, k) ->
+        (X (n, 48), weight deviation (n,), flux excess (n,))."""
+        import torch
+        n = where.shape[0]
+        if where.dtype != torch.int32 or not where.is_contiguous() or tuple(where.shape[1:]) != (4,):
+            raise ValueError("where must be a contiguous int32 tensor of shape (n, 4)")
+        X = torch.empty((n, 48), dtype=torch.float32, device=u.device)
+        dev = torch.empty(n, dtype=torch.float32, device=u.device)
+        ex = torch.empty(n, dtype=torch.float32, device=u.device)
+        _check(lib().wombat_weno_router_sample(self.h, self._ptr(u, "u"), C.c_void_p(where.data_ptr()), n,
+                                               C.c_void_p(X.data_ptr()), C.c_void_p(dev.data_ptr()),
+                                               C.c_void_p(ex.data_ptr())), self.h)
+        return X, dev, ex
+
     def divb(self, u):
         mx, l1 = C.c_double(), C.c_double()
         _check(lib().wombat_weno_divb(self.h, self._ptr(u, "u"), C.byref(mx), C.byref(l1)), self.h)
@@ -297,3 +335,42 @@ class Batch:
                                                      cache_path.encode() if cache_path else None,
                                                      C.byref(ms)))
         return ms.value
+
+
+# ---- MLP of the learned router (stream = torch's current stream) ----
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def mlp_param_count():
+    return int(lib().wombat_mlp_param_count())
+
+
+def mlp_forward(theta, X):
+    import torch
+    n = X.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().wombat_mlp_forward(_stream(), C.c_void_p(theta.data_ptr()), C.c_void_p(X.data_ptr()), n,
+                                    C.c_void_p(out.data_ptr())))
+    return out
+
+
+def mlp_grad(theta, X, t, work=None):
+    import torch
+    n = X.shape[0]
+    if work is None:
+        work = torch.empty(int(lib().wombat_mlp_grad_workspace(n)), dtype=torch.float32, device=X.device)
+    g = torch.empty(mlp_param_count(), dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().wombat_mlp_grad(_stream(), C.c_void_p(theta.data_ptr()), C.c_void_p(X.data_ptr()),
+                                 C.c_void_p(t.data_ptr()), n, C.c_void_p(work.data_ptr()),
+                                 C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr())))
+    return g, loss
+
+
+def mlp_adam(theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().wombat_mlp_adam(_stream(), C.c_void_p(theta.data_ptr()), C.c_void_p(m.data_ptr()),
+                                 C.c_void_p(v.data_ptr()), C.c_void_p(grad.data_ptr()), int(step),
+                                 float(lr), float(beta1), float(beta2), float(eps)))

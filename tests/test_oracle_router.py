@@ -1,5 +1,5 @@
-"""Pins of the oracle parts behind the learned router: the weight-deviation
-label, the linear component-wise flux, the stencil features and the MLP
+"""Pins of the oracle parts behind the learned router: the weight deviation,
+the flux-excess label, the linear component-wise flux, the stencil features and the MLP
 gradient (against finite differences, not against its own formulas)."""
 import numpy as np
 import pytest
@@ -49,23 +49,72 @@ def test_weight_deviation_label(orc):
     assert np.array_equal(F0, F1)
 
 
-def test_features_invariances():
+def test_flux_excess_label(orc):
+    # uniform stencil: both fluxes are the physical flux -> rounding only
+    W0 = np.array([1.0, 0.5, 0.2, -0.1, 0.3, 0.2, 0.1, 1.0])
+    assert orc.flux_excess(np.tile(orc.prim_to_cons(W0), (6, 1))) < 1e-14
+    # smooth waves: the two fifth-order fluxes differ at O(h^5), so the
+    # excess falls by ~2^5 per halving of the cell width
+    worst = []
+    for lam in (32, 64, 128):
+        ex = []
+        for ph in np.linspace(0, 2 * np.pi, 8, endpoint=False):
+            Us = np.array([orc.prim_to_cons(W0 * (1 + 0.1 * np.sin(2 * np.pi * j / lam + ph + np.arange(8))))
+                           for j in range(6)])
+            ex.append(orc.flux_excess(Us))
+        worst.append(max(ex))
+    assert worst[0] < 1e-5
+    assert worst[0] / worst[1] > 16 and worst[1] / worst[2] > 16, worst
+    # tiny amplitude: linear weights and nearly equal speeds
+    assert orc.flux_excess(smooth_stencil(orc, 1e-5)) < 1e-8
+    # a Brio-Wu jump between cells 2 and 3: O(0.1)
+    W1 = np.array([1.0, 0, 0, 0, 0.75, 1.0, 0, 1.0])
+    W2 = np.array([0.125, 0, 0, 0, 0.75, -1.0, 0, 0.1])
+    Us = np.array([orc.prim_to_cons(W1 if j < 3 else W2, 2.0) for j in range(6)])
+    assert orc.flux_excess(Us, gamma=2.0) > 1e-2
+
+
+def test_fast_speed_matches_c_oracle(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        W = np.concatenate([[rng.uniform(0.1, 3)], rng.normal(size=3), rng.normal(size=3), [rng.uniform(0.05, 3)]])
+        U = orc.prim_to_cons(W)
+        assert abs(mlp.fast_speed(U) - orc.wave_speeds(U, 0)[0]) < 1e-13 * orc.wave_speeds(U, 0)[0]
+
+
+def test_features_definition(orc):
+    W0 = np.array([1.0, 0.5, 0.2, -0.1, 0.3, 0.2, 0.1, 1.0])
+    U0 = orc.prim_to_cons(W0)
+    L = lambda y, S: 1 + 0.25 * np.log10(y / S + 1e-8)
+    # uniform stencil: every difference is 0 -> L(0) = 1 + log10(1e-8)/4 = -1
+    x = mlp.features(np.tile(U0, (6, 1))).reshape(8, 6)
+    assert np.allclose(x, -1.0, atol=1e-15)
+    # only rho alternates 1, 1.1, 1, ...: |differences| 0.1, 0.2, 0.4, 0.8,
+    # 1.6, interface jump 0.1; mass scale max rho = 1.1
+    st = np.tile(U0, (6, 1))
+    st[:, 0] = [1.0, 1.1, 1.0, 1.1, 1.0, 1.1]
+    x = mlp.features(st).reshape(8, 6)
+    assert np.allclose(x[0], [L(0.1, 1.1), L(0.1, 1.1), L(0.2, 1.1), L(0.4, 1.1), L(0.8, 1.1), L(1.6, 1.1)],
+                       atol=1e-12)
+    assert np.allclose(x[1:], -1.0, atol=1e-15)
+    # energy quadratic in the cell index: third and higher differences vanish
+    st = np.tile(U0, (6, 1))
+    st[:, 7] = U0[7] + 0.125 * np.arange(6) ** 2
+    x = mlp.features(st).reshape(8, 6)[7]
+    assert np.allclose(x[3:], -1.0, atol=1e-12) and x[2] > x[3] + 1
+    # a resolved sine (kh = 2 pi / 64): the fifth difference sits ~(kh)^4,
+    # i.e. ~4 decades (one feature unit), below the first
+    lam = 64
+    st = np.array([orc.prim_to_cons(W0 * (1 + 0.1 * np.sin(2 * np.pi * j / lam + np.arange(8)))) for j in range(6)])
+    x = mlp.features(st).reshape(8, 6)
+    assert np.all(x[:, 5] - x[:, 0] < -0.75)
+    # random physical stencils: finite, at least -1
     rng = np.random.default_rng(1)
-    s = rng.normal(size=(5, 6, 8))
-    x = mlp.features(s)
-    assert x.shape == (5, 48)
-    assert np.abs(x).max() <= 1.0 + 1e-15
-    # each variable attains |x| = 1 somewhere on the stencil
-    assert np.allclose(np.abs(x.reshape(5, 8, 6)).max(-1), 1.0)
-    # invariant under per-variable shifts and positive scalings, odd under sign flips
-    a = rng.uniform(0.1, 10, size=8)
-    b = rng.normal(size=8)
-    assert np.allclose(mlp.features(s * a + b), x, atol=1e-12)
-    assert np.allclose(mlp.features(-s), -x, atol=1e-12)
-    # a constant variable gives zeros
-    s2 = s.copy()
-    s2[:, :, 3] = 7.0
-    assert np.all(mlp.features(s2).reshape(5, 8, 6)[:, 3] == 0.0)
+    for _ in range(10):
+        st = np.array([orc.prim_to_cons(W0 * (1 + 0.3 * rng.normal(size=8)) * [1, 1, 1, 1, 1, 1, 1, 0] +
+                                        [0, 0, 0, 0, 0, 0, 0, 1]) for _ in range(6)])
+        x = mlp.features(st)
+        assert np.all(np.isfinite(x)) and x.min() >= -1.0
 
 
 def test_mlp_gradient_matches_finite_differences():
@@ -88,3 +137,28 @@ def test_mlp_pack_roundtrip_and_size():
     theta = mlp.init_params(0)
     assert theta.size == mlp.NPARAM == 2657
     assert np.array_equal(mlp.pack(*mlp.unpack(theta)), theta)
+
+
+def test_linear_rhs_converges_at_fifth_order(orc):
+    # The all-linear scheme (the router's cheap flux everywhere) is a linear
+    # fifth-order scheme: 1-D Alfven wave over one period, n = 16, 32, 64.
+    from paper_1808_10633_amd import inputs as I
+    import math
+    errs = []
+    for n in (16, 32, 64):
+        u, speed = I.linear_wave_1d("alfven", n, amp=1e-5)
+        g = orc.Grid(n, dx=1.0 / n)
+        T = 1.0 / abs(speed)
+        nst = int(math.ceil(T / (0.4 / n / 2.0)))
+        dt = T / nst
+        for _ in range(nst):
+            k1 = orc.rhs_linear(g, u)
+            k2 = orc.rhs_linear(g, u + 0.5 * dt * k1)
+            k3 = orc.rhs_linear(g, u + 0.5 * dt * k2)
+            k4 = orc.rhs_linear(g, u + dt * k3)
+            u = u + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        ue, _ = I.linear_wave_1d("alfven", n, amp=1e-5, t=T)
+        e = np.abs(g.interior(u) - g.interior(ue)).mean(axis=(1, 2, 3))
+        errs.append(math.sqrt((e ** 2).sum()))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert (order > 4.7).all(), (errs, order)
