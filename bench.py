@@ -29,9 +29,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 
 # HBM bytes per launch of the timed sweep kernel from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE runs (scaled by a 1 GiB copy; see profiles/), valid only for
-# the sweep source they were taken on (sha256 of ww_sweep.hip + ww_internal.h).
+# the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
+# and ww_internal.h).
 MEASURED_TRAFFIC = {
-    ("8adfd3dfffe20d8d", "fp64", 512): {"read": 24.04e9, "write": 7.83e9,
+    ("7490f409550ccfca", "fp64", 512): {"read": 24.04e9, "write": 7.83e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -39,7 +40,8 @@ MEASURED_TRAFFIC = {
 def sweep_source_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_1808_10633_amd", "csrc")
-    src = b"".join(open(os.path.join(d, f), "rb").read() for f in ("ww_sweep.hip", "ww_internal.h"))
+    src = b"".join(open(os.path.join(d, f), "rb").read()
+                   for f in ("ww_sweep.hip", "ww_sweep_dev.h", "ww_internal.h"))
     return hashlib.sha256(src).hexdigest()[:16]
 
 
@@ -60,7 +62,7 @@ def parse():
                     help="full-WENO FP32 steps that shock the learned-form turbulence")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--train-steps", type=int, default=3000)
-    ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--cpu-n", type=int, default=112)
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the event timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")

@@ -259,31 +259,44 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
  * component-wise flux (one Lax-Friedrichs speed max(|v_n| + c_f) over the
  * stencil, weights (2,-13,47,27,-3)/60 on F^+ and the mirror on F^-).
  *
- * MLP: 48 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid).  Inputs: the six cells
- * i-2..i+3 of the interface, 8 conserved variables each in the sweep frame
- * (rho, m_n, m_t1, m_t2, B_n, B_t1, B_t2, E), each variable normalised over
- * the stencil as (q - mean)/(max|q - mean| + 1e-5 max|q| + 1e-30), ordered
- * x[v*6 + j].
+ * MLP: 48 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid).  Inputs: from the six
+ * cells i-2..i+3 of the interface, for each of the 8 conserved variables in
+ * the sweep frame (rho, m_n, m_t1, m_t2, B_n, B_t1, B_t2, E), six values
+ * x[v*6 + j] = 1 + log2m(y_j / S_v + 1e-8) log10(2)/4 with y_0 the largest
+ * first difference on the stencil, y_1 the jump across the interface,
+ * y_2..y_4 the largest second to fourth and y_5 the fifth difference
+ * (absolute values); S_v the stencil scale of the variable (see
+ * wombat_weno_router_sample); log2m Mitchell's log2 (exponent plus mantissa
+ * fraction of the FP32 value).
  * Parameters: one FP32 device vector of wombat_mlp_param_count() = 2657
  * values: W1 (32x48 row-major [out][in]), b1 (32), W2 (32x32), b2 (32),
  * w3 (32), b3.  Products run in BF16 on MFMA with FP32 accumulation.
  * Training label ("troubled"): the flux excess below exceeds a threshold
- * (1e-4 by default in the Python training code).
+ * (1e-3 by default in the Python training code).
  * ------------------------------------------------------------------------ */
 
-/* Route the sweeps of an FP32 context through the router: d_theta
- * (device, caller-owned, must stay valid while set; NULL switches the
- * router off), threshold in (0,1): an interface is troubled when
- * sigmoid(logit) > threshold (NaN counts as troubled).  mode 0 routes; +1
- * sends every interface to the full flux and -1 every one to the linear
- * flux (through the same kernel).  The first call with a non-NULL d_theta
- * allocates one state-sized backup array (kept until destroy).
- * Full WENO is the fallback: wombat_weno_step with mode 0 keeps u^n in that
- * array, and if the routed step leaves a non-physical cell it is redone
- * from u^n with full characteristic WENO on every interface (counted in
- * router_stats).  Stages and rhs calls have no fallback.
+/* Route the sweeps of an FP32 context through the router.  d_theta
+ * (device FP32, wombat_mlp_param_count() values, read on the context's
+ * stream during this call: a copy packed as BF16 MFMA operands is kept, so
+ * later changes to d_theta need another call; NULL switches routing off),
+ * threshold in (0,1): an interface is troubled when sigmoid(logit) >
+ * threshold (NaN counts as troubled).  mode 0 routes: smooth interfaces
+ * take the linear flux in the routed sweep, troubled ones are queued and
+ * take the full flux in a second pass; +1 sends every interface to the full
+ * flux (the plain sweep) and -1 every one to the linear flux (the routed
+ * sweep without evaluating the network).  The first call with a
+ * non-NULL d_theta allocates one state-sized backup array, the packed
+ * parameters, a queue of one 8-byte entry per face of the largest sweep and
+ * one decision byte per face of every sweep (kept until destroy).
+ * wombat_weno_step evaluates the network at its first stage and reuses
+ * those decisions (one byte per face, kept in the context) for its other
+ * three stages; wombat_weno_stage and wombat_weno_rhs evaluate it on every
+ * call.  Full WENO is the fallback: wombat_weno_step with mode 0 keeps u^n
+ * in the backup array, and if the routed step leaves a non-physical cell it
+ * is redone from u^n with full characteristic WENO on every interface
+ * (counted in router_stats).  Stages and rhs calls have no fallback.
  * WW_ERR_UNSUPPORTED on FP64 contexts, WW_ERR_INVALID_ARG for a threshold
- * or mode out of range, WW_ERR_OOM if the backup cannot be allocated. */
+ * or mode out of range, WW_ERR_OOM if the buffers cannot be allocated. */
 int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double threshold, int mode);
 
 /* Interfaces routed to the linear flux by the three sweeps of the last
@@ -301,9 +314,10 @@ int wombat_weno_router_stats(wombat_weno_t *ctx, int64_t *smooth, int64_t *total
  *                 field, either side of eq. (1)) from (0.1, 0.6, 0.3);
  *   d_excess[s]   the flux excess max_c |Fc_full - Fc_lin| / (a S_c): the
  *                 characteristic flux against the linear flux, with a the
- *                 largest |v_n| + c_f on the stencil and S = max rho (mass),
- *                 max(|m| + rho a) (momenta), max(|B| + sqrt(rho) a)
- *                 (fields), max E (energy) over the stencil.
+ *                 largest |v_n| + c_f on the stencil and the stencil scales
+ *                 S = max rho (mass), max(|m|_1 + rho a) (momenta),
+ *                 max |B|_1 + sqrt(max rho) a (fields), max E (energy),
+ *                 |.|_1 the sum of absolute components.
  * A position outside the box (dir not an active axis, a face index outside
  * 0..n_dir, a transverse index outside 0..n-1) gets NaN in all three
  * outputs; the others are unaffected.  WW_ERR_INVALID_ARG for NULL

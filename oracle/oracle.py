@@ -203,8 +203,9 @@ def flux_excess(Us, gamma=5.0 / 3.0, eps=1e-6):
     to a stencil scale, maximised over the components:
 
       r = max_c |Fhat_c - Flin_c| / (a S_c),  a = max_j (|v_n| + c_f),
-      S = max rho (mass), max (|m| + rho a) (momenta), max (|B| + sqrt(rho) a)
-          (fields), max E (energy), maxima over the six stencil cells.
+      S = max rho (mass), max (|m|_1 + rho a) (momenta),
+          max |B|_1 + sqrt(max rho) a (fields), max E (energy),
+    maxima over the six stencil cells, |.|_1 the sum of absolute components.
     """
     Us = np.asarray(Us, dtype=np.float64)
     Ff = interface_flux(Us, gamma, eps)
@@ -212,12 +213,11 @@ def flux_excess(Us, gamma=5.0 / 3.0, eps=1e-6):
     a = 0.0
     for j in range(6):
         cf = wave_speeds(Us[j], 0, gamma)[0]
-        a = max(a, abs(Us[j, 1] / Us[j, 0]) + cf)
+        a = max(a, abs(Us[j, 1]) / Us[j, 0] + cf)
     rho = Us[:, 0]
-    m = np.sqrt((Us[:, 1:4] ** 2).sum(1))
-    b = np.sqrt((Us[:, 4:7] ** 2).sum(1))
-    S = np.array([rho.max(), (m + rho * a).max(), (m + rho * a).max(), (m + rho * a).max(), np.inf,
-                  (b + np.sqrt(rho) * a).max(), (b + np.sqrt(rho) * a).max(), Us[:, 7].max()])
+    sm = (np.abs(Us[:, 1:4]).sum(1) + rho * a).max()
+    sb = np.abs(Us[:, 4:7]).sum(1).max() + np.sqrt(rho.max()) * a
+    S = np.array([rho.max(), sm, sm, sm, np.inf, sb, sb, Us[:, 7].max()])
     return float((np.abs(Ff - Fl) / (a * S)).max())
 
 

@@ -30,12 +30,17 @@ struct wombat_weno {
     double *hsmall;        // pinned host mirror of dsmall (16 doubles + flag)
     int nblk;
     hipEvent_t ev[2];      // kernel timing
-    const float *router;   // learned-router parameters (caller-owned), or NULL
+    int router;            // learned routing switched on
+    char *router_pk;       // its parameters, packed in MFMA operand order
     float router_thr;      // logit threshold of "troubled"
     int router_force;      // 0 routed, +1 all full WENO, -1 all linear (same kernel)
     int32_t *nsmooth;      // per-block smooth counts of the last learned sweeps
     long nsm_blocks[3];
     void *backup;          // u at the start of a routed step (allocated with the router)
+    unsigned long long *queue;   // troubled interfaces of the current routed sweep
+    int32_t *qcount;       // its length
+    unsigned char *rmask;  // routing decisions per face, the three directions one after another
+    int router_reuse;      // stages 2-4 of a step: reuse the decisions of its first stage
     int64_t fallbacks;     // routed steps redone with full WENO
     hipStream_t st;
     int sticky;            // a HIP error happened: every later call fails
@@ -176,6 +181,10 @@ void release(wombat_weno_t *c)
     if (c->hsmall) (void)hipHostFree(c->hsmall);
     if (c->nsmooth) (void)hipFree(c->nsmooth);
     if (c->backup) (void)hipFree(c->backup);
+    if (c->router_pk) (void)hipFree(c->router_pk);
+    if (c->queue) (void)hipFree(c->queue);
+    if (c->rmask) (void)hipFree(c->rmask);
+    if (c->qcount) (void)hipFree(c->qcount);
     for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
@@ -214,15 +223,24 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
     int rc = fill_ghosts_t<T>(c, us);
     if (rc) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
+    if (c->router && c->router_force > 0) {
+        // all interfaces full: the plain sweep (same face arithmetic); no smooth ones
+        const long tot = c->nsm_blocks[0] + c->nsm_blocks[1] + c->nsm_blocks[2];
+        WW_CHECK(c, hipMemsetAsync(c->nsmooth, 0, sizeof(int32_t) * (tot > 0 ? tot : 1), c->st));
+    }
     for (int d = 0; d < 3; ++d) {
         if (!c->G.act[d]) continue;
         if constexpr (sizeof(T) == 4) {
-            if (c->router) {
+            if (c->router && c->router_force <= 0) {
                 int32_t *ns = c->nsmooth;
-                for (int e = 0; e < d; ++e) ns += c->nsm_blocks[e];
-                WW_CHECK(c, ww::launch_learned_sweep(d, (const float *)us, (float *)c->ff[d], c->G, c->F[d], P,
-                                                     c->router, c->router_thr, c->router_force, ns,
-                                                     c->st));
+                unsigned char *mk = c->rmask;
+                for (int e = 0; e < d; ++e) {
+                    ns += c->nsm_blocks[e];
+                    if (c->G.act[e]) mk += c->F[e].sc;
+                }
+                WW_CHECK(c, ww::launch_routed_sweep(d, (const float *)us, (float *)c->ff[d], c->G, c->F[d], P,
+                                                    c->router_pk, c->router_thr, c->router_force, ns,
+                                                    c->queue, c->qcount, mk, c->router_reuse, c->st));
                 continue;
             }
         }
@@ -349,7 +367,7 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
     if (cfg->precision == WW_FP32_MIXED) {
         long tot = 0;
         for (int d = 0; d < 3; ++d) {
-            c->nsm_blocks[d] = c->G.act[d] ? ww::learned_sweep_blocks(d, c->F[d]) : 0;
+            c->nsm_blocks[d] = c->G.act[d] ? ww::routed_sweep_blocks(d, c->F[d]) : 0;
             tot += c->nsm_blocks[d];
         }
         if (dev_alloc((void **)&c->nsmooth, sizeof(int32_t) * (tot > 0 ? tot : 1)) != hipSuccess)
@@ -478,14 +496,20 @@ int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0, vo
 
 namespace {
 
+// The four stages of a step.  With routing on, the network is evaluated at
+// the first stage and its decisions reused for the other three.
 int rk4_stages(wombat_weno_t *ctx, void *d_u, double dt)
 {
     void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
     int rc;
+    ctx->router_reuse = 0;
     if ((rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A))) return rc;
-    if ((rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, B))) return rc;
-    if ((rc = wombat_weno_stage(ctx, 2, dt, d_u, B, acc, A))) return rc;
-    return wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u);
+    ctx->router_reuse = ctx->router ? 1 : 0;
+    if (!(rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, B)) &&
+        !(rc = wombat_weno_stage(ctx, 2, dt, d_u, B, acc, A)))
+        rc = wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u);
+    ctx->router_reuse = 0;
+    return rc;
 }
 
 }  // namespace
@@ -585,18 +609,42 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
     if (rc) return rc;
     if (ctx->cfg.precision != WW_FP32_MIXED)
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs on FP32 contexts");
-    if (!d_theta) { ctx->router = nullptr; return WW_OK; }
+    if (!d_theta) { ctx->router = 0; return WW_OK; }
     if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
     if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");
+    DevGuard dg(ctx->cfg.device);
     if (!ctx->backup) {
-        DevGuard dg(ctx->cfg.device);
         if (dev_alloc(&ctx->backup, ctx->elems * ctx->esize) != hipSuccess) {
             ctx->backup = nullptr;
             (void)hipGetLastError();
             return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the routed-step backup");
         }
     }
-    ctx->router = d_theta;
+    if (!ctx->router_pk) {
+        if (dev_alloc((void **)&ctx->router_pk, ww::MLP_PACKED_BYTES) != hipSuccess) {
+            ctx->router_pk = nullptr;
+            (void)hipGetLastError();
+            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the router parameters");
+        }
+    }
+    if (!ctx->queue) {
+        long most = 1, all = 1;
+        for (int d = 0; d < 3; ++d)
+            if (ctx->G.act[d]) { most = std::max(most, ctx->F[d].sc); all += ctx->F[d].sc; }
+        if (dev_alloc((void **)&ctx->queue, sizeof(unsigned long long) * most) != hipSuccess ||
+            dev_alloc((void **)&ctx->qcount, sizeof(int32_t)) != hipSuccess ||
+            dev_alloc((void **)&ctx->rmask, all) != hipSuccess) {
+            if (ctx->queue) (void)hipFree(ctx->queue);
+            if (ctx->qcount) (void)hipFree(ctx->qcount);
+            ctx->queue = nullptr;
+            ctx->qcount = nullptr;
+            ctx->rmask = nullptr;
+            (void)hipGetLastError();
+            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the troubled-interface queue");
+        }
+    }
+    WW_CHECK(ctx, ww::launch_pack_mlp(d_theta, ctx->router_pk, ctx->st));
+    ctx->router = 1;
     ctx->router_thr = (float)std::log(threshold / (1.0 - threshold));
     ctx->router_force = mode;
     return WW_OK;

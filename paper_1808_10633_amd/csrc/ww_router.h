@@ -16,9 +16,16 @@ hipError_t launch_mlp_adam(float *th, float *m, float *v, const float *grad, int
 template <typename T>
 hipError_t launch_router_sample(const T *u, const Geom &G, const Phys &P, const int32_t *where,
                                 int n, float *X, float *dev, float *ex, hipStream_t st);
-long learned_sweep_blocks(int dir, const FaceBox &F);
-hipError_t launch_learned_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
-                                const Phys &P, const float *th, float thr, int force,
-                                int32_t *nsmooth, hipStream_t st);
+constexpr int MLP_PACKED_BYTES = 10 * 64 * 8 + 25 * 64 * 4;
+hipError_t launch_pack_mlp(const float *th, char *pk, hipStream_t st);
+long routed_sweep_blocks(int dir, const FaceBox &F);
+// Routed sweep of direction dir (force 0 routed, -1 all linear), then the
+// full-WENO pass over the queued troubled interfaces.  queue holds at least
+// F.sc entries; *qcount is cleared on st first.  mask (F.sc bytes) receives
+// the decisions, or supplies them when reuse is set.
+hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
+                              const Phys &P, const char *pk, float thr, int force, int32_t *nsmooth,
+                              unsigned long long *queue, int32_t *qcount, unsigned char *mask, int reuse,
+                              hipStream_t st);
 
 }  // namespace ww

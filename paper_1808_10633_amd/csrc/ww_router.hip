@@ -1,17 +1,19 @@
 // ww_router.hip -- the learned troubled-interface router.
 //
-// An MLP 48 -> 32 -> 32 -> 1 (ReLU, sigmoid) reads the normalised six-cell
-// stencil of an interface and predicts whether the full characteristic WENO
-// flux (arXiv:1808.10633 Sec. 2.1) is needed there, i.e. whether some WENO
-// weight departs from its linear value by more than 1e-2.  Interfaces called
-// smooth take the linear fifth-order component-wise flux instead.
+// An MLP 48 -> 32 -> 32 -> 1 (ReLU, sigmoid) reads log-scaled difference
+// magnitudes of the six-cell stencil of an interface and predicts whether
+// the full characteristic WENO flux (arXiv:1808.10633 Sec. 2.1) is needed
+// there, i.e. whether it departs from the linear fifth-order component-wise
+// flux by more than a set fraction of the local flux scale (the flux
+// excess).  Interfaces called smooth take the linear flux instead.
 //
 // Matrix products run on MFMA (v_mfma_f32_16x16x16_bf16: BF16 operands, FP32
 // accumulation).  Layers are computed transposed, Z^T = W X^T, so that the
 // output registers of one layer (lane l holds rows 4(l/16)+i, column l%16 of
 // a 16x16 tile) are exactly the B operand of the next layer: no shuffles.
 // Parameters are one FP32 vector of 2657 values: W1 (32x48, [out][in]), b1,
-// W2 (32x32), b2, w3 (32), b3; BF16 copies are made per block.
+// W2 (32x32), b2, w3 (32), b3.  Training kernels convert them per block; the
+// routed sweep reads a copy packed once in the per-lane operand order.
 #include "ww_router.h"
 #include "ww_sweep_dev.h"
 
@@ -66,57 +68,199 @@ __device__ __forceinline__ void load_mlp(const float *__restrict__ th, MlpRegs &
     R.b3 = th[OB3];
 }
 
+// Parameters packed for the routed sweep: [10][64] BF16 operand fragments
+// (a1 by (ot, kt), then a2 by (ot, kt)) followed by [25][64] floats (b1, b2,
+// w3 by (ot, i), then b3), item-major so that a wave reads every item with
+// one coalesced load and converts nothing.
+__global__ __launch_bounds__(64) void pack_mlp_kernel(const float *__restrict__ th, char *__restrict__ pk)
+{
+    const int l = threadIdx.x;
+    MlpRegs R;
+    load_mlp(th, R);
+    bf4 *pa = (bf4 *)pk;
+    float *pf = (float *)(pk + 10 * 64 * 8);
+    int t = 0;
+    for (int ot = 0; ot < 2; ++ot)
+        for (int kt = 0; kt < 3; ++kt) pa[64 * t++ + l] = R.a1[ot][kt];
+    for (int ot = 0; ot < 2; ++ot)
+        for (int kt = 0; kt < 2; ++kt) pa[64 * t++ + l] = R.a2[ot][kt];
+    t = 0;
+    for (int ot = 0; ot < 2; ++ot)
+        for (int i = 0; i < 4; ++i) {
+            pf[64 * (t + 0) + l] = R.b1[ot][i];
+            pf[64 * (t + 8) + l] = R.b2[ot][i];
+            pf[64 * (t + 16) + l] = R.w3[ot][i];
+            ++t;
+        }
+    pf[64 * 24 + l] = R.b3;
+}
+
+__device__ __forceinline__ void load_mlp_packed(const char *__restrict__ pk, MlpRegs &R)
+{
+    const int l = threadIdx.x & 63;
+    const bf4 *pa = (const bf4 *)pk;
+    const float *pf = (const float *)(pk + 10 * 64 * 8);
+    int t = 0;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int kt = 0; kt < 3; ++kt) R.a1[ot][kt] = pa[64 * t++ + l];
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) R.a2[ot][kt] = pa[64 * t++ + l];
+    t = 0;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            R.b1[ot][i] = pf[64 * (t + 0) + l];
+            R.b2[ot][i] = pf[64 * (t + 8) + l];
+            R.w3[ot][i] = pf[64 * (t + 16) + l];
+            ++t;
+        }
+    R.b3 = pf[64 * 24 + l];
+}
+
+// Four floats as four BF16 (round to nearest even, hardware conversion).
+__device__ __forceinline__ bf4 pack_bf4(float a, float b, float c, float d)
+{
+    typedef __bf16 h4 __attribute__((ext_vector_type(4)));
+    const h4 v = { (__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d };
+    return __builtin_bit_cast(bf4, v);
+}
+
+// Forward pass of 16 samples, rows g[m*XS + k] (BF16), m = 0..15; returns
+// the logit of sample l%16 (in every lane).  If a1s/a2s are given, the
+// pre-activations (with bias) of sample m are stored at [(16 st + m)*32 ..].
+__device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R, float *a1s, float *a2s,
+                                           int st)
+{
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    f4 z1[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+    for (int kt = 0; kt < 3; ++kt) {
+        const bf4 bx = *(const bf4 *)(g + r * XS + 16 * kt + 4 * q);
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+            z1[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[ot][kt], bx, z1[ot], 0, 0, 0);
+    }
+    bf4 h1[2];
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float a = z1[ot][i] + R.b1[ot][i];
+            if (a1s) a1s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
+            h1[ot][i] = f2bf(fmaxf(a, 0.f));
+        }
+    f4 z2[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+            z2[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[ot][kt], h1[kt], z2[ot], 0, 0, 0);
+    float part = 0.f;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float a = z2[ot][i] + R.b2[ot][i];
+            if (a2s) a2s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
+            part += R.w3[ot][i] * fmaxf(a, 0.f);
+        }
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    return part + R.b3;
+}
+
 // Forward pass of the 64 samples of this wave, rows xs[m*XS + k] (BF16),
-// m = 0..63.  lg[st] receives the logit of sample 16*st + l%16.  If a1s/a2s
-// are given, the pre-activations (with bias) are stored there as [m][32].
+// m = 0..63.  lg[st] receives the logit of sample 16*st + l%16.
 __device__ __forceinline__ void mlp_wave(const short *xs, const MlpRegs &R, float (&lg)[4],
                                          float *a1s, float *a2s)
 {
-    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-        const int m = 16 * st + r;
-        f4 z1[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
-#pragma unroll
-        for (int kt = 0; kt < 3; ++kt) {
-            const bf4 bx = *(const bf4 *)(xs + m * XS + 16 * kt + 4 * q);
-#pragma unroll
-            for (int ot = 0; ot < 2; ++ot)
-                z1[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[ot][kt], bx, z1[ot], 0, 0, 0);
-        }
-        bf4 h1[2];
-#pragma unroll
-        for (int ot = 0; ot < 2; ++ot)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float a = z1[ot][i] + R.b1[ot][i];
-                if (a1s) a1s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
-                h1[ot][i] = f2bf(fmaxf(a, 0.f));
-            }
-        f4 z2[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-            for (int ot = 0; ot < 2; ++ot)
-                z2[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[ot][kt], h1[kt], z2[ot], 0, 0, 0);
-        float part = 0.f;
-#pragma unroll
-        for (int ot = 0; ot < 2; ++ot)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float a = z2[ot][i] + R.b2[ot][i];
-                if (a2s) a2s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
-                part += R.w3[ot][i] * fmaxf(a, 0.f);
-            }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        lg[st] = part + R.b3;
-    }
+    for (int st = 0; st < 4; ++st) lg[st] = mlp_group(xs + 16 * st * XS, R, a1s, a2s, st);
 }
 
 __device__ __forceinline__ float pick4(const float (&v)[4], int i)
 {
     return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+}
+
+// ---------------------------------------------------------------- stencil
+
+// Stencil scales shared by the features and the flux excess: a = the
+// largest |v_n| + c_f on the stencil; S = max rho (mass), max(|m|_1 + rho a)
+// (momenta), max |B|_1 + sqrt(max rho) a (fields), max E (energy), returned
+// as reciprocals is[4].  (|.|_1: sum of the absolute components.)
+template <typename T>
+__device__ __forceinline__ void stencil_scales(const T *__restrict__ sq, int qs, int off, int cstr,
+                                               T &a, T (&is)[4])
+{
+#define QS(q, j) sq[(q) * qs + off + (j) * cstr]
+    a = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) a = fmax(a, fabs(QS(1, j)) * QS(9, j) + QS(10, j));
+    T sr = T(0), sm = T(0), sb = T(0), se = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const T r = QS(0, j);
+        sr = fmax(sr, r);
+        sm = fmax(sm, fabs(QS(1, j)) + fabs(QS(2, j)) + fabs(QS(3, j)) + r * a);
+        sb = fmax(sb, fabs(QS(4, j)) + fabs(QS(5, j)) + fabs(QS(6, j)));
+        se = fmax(se, QS(7, j));
+    }
+#undef QS
+    sb += sqrt(sr) * a;
+    is[0] = sw::frcp(sr);
+    is[1] = sw::frcp(sm);
+    is[2] = sw::frcp(sb);
+    is[3] = sw::frcp(se);
+}
+
+// log2 by Mitchell's approximation (exponent plus the mantissa fraction,
+// read off the bit pattern), exact at powers of two, error below 0.087.
+__device__ __forceinline__ float log2m(float y)
+{
+    return (float)__float_as_int(y) * 1.1920928955078125e-07f - 127.0f;
+}
+
+// Router features of one interface from its six staged cells (i-2..i+3),
+// six per sweep-frame conserved variable v, stored x[v*6 + j], each
+// L(y) = 1 + log2m(y / S_v + 1e-8) log10(2) / 4 of
+//   j = 0     the largest first difference on the stencil,
+//   j = 1     the jump across the interface |q_3 - q_2|,
+//   j = 2..4  the largest second, third and fourth difference,
+//   j = 5     the fifth difference (absolute values throughout).
+// On smooth data the m-th difference falls like (kh)^m, so smoothness and
+// amplitude are both differences of O(1) features, which BF16 carries.
+template <typename T>
+__device__ __forceinline__ void router_features(const T *__restrict__ sq, int qs, int off, int cstr,
+                                                float (&x)[48])
+{
+#define QF(q, j) sq[(q) * qs + off + (j) * cstr]
+    T a, is[4];
+    stencil_scales<T>(sq, qs, off, cstr, a, is);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const T iv = is[v == 0 ? 0 : v < 4 ? 1 : v < 7 ? 2 : 3];
+        T d[6], y[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) d[j] = QF(v, j);
+        y[1] = fabs(d[3] - d[2]);
+#pragma unroll
+        for (int m = 1; m <= 5; ++m) {           // d <- its next difference
+            T mx = T(0);
+#pragma unroll
+            for (int j = 0; j + m < 6; ++j) { d[j] = d[j + 1] - d[j]; mx = fmax(mx, fabs(d[j])); }
+            y[m == 1 ? 0 : m] = mx;
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            x[v * 6 + j] = 1.0f + 0.0752574989f * log2m((float)(y[j] * iv + T(1e-8)));
+    }
+#undef QF
 }
 
 // ---------------------------------------------------------------- kernels
@@ -250,31 +394,18 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ th, f
 
 // Relative excess of the full characteristic flux ff over the linear flux
 // fl at one interface (both sweep-frame, rho, m_n, m_t1, m_t2, B_t1, B_t2,
-// E): max over components of |ff - fl| / S, with a the largest |v_n| + c_f
-// on the stencil and the scales S = a max rho (mass), a max(|m| + rho a)
-// (momenta), a max(|B| + sqrt(rho) a) (fields), a max E (energy).
+// E): max over components of |ff - fl| / (a S) with the stencil scales.
 template <typename T>
 __device__ T flux_excess(const T *__restrict__ sq, int qs, int off, int cstr, const T (&ff)[7],
                          const T (&fl)[7])
 {
-#define QE(q, j) sq[(q) * qs + off + (j) * cstr]
-    T a = T(0);
-    for (int j = 0; j < 6; ++j) a = fmax(a, fabs(QE(1, j) * QE(9, j)) + QE(10, j));
-    T sr = T(0), sm = T(0), sb = T(0), se = T(0);
-    for (int j = 0; j < 6; ++j) {
-        const T r = QE(0, j);
-        const T m = sqrt(QE(1, j) * QE(1, j) + QE(2, j) * QE(2, j) + QE(3, j) * QE(3, j));
-        const T b = sqrt(QE(4, j) * QE(4, j) + QE(5, j) * QE(5, j) + QE(6, j) * QE(6, j));
-        sr = fmax(sr, r);
-        sm = fmax(sm, m + r * a);
-        sb = fmax(sb, b + sqrt(r) * a);
-        se = fmax(se, QE(7, j));
-    }
-#undef QE
-    const T sc[7] = { sr, sm, sm, sm, sb, sb, se };
+    T a, is[4];
+    stencil_scales<T>(sq, qs, off, cstr, a, is);
+    const int g[7] = { 0, 1, 1, 1, 2, 2, 3 };
     T ex = T(0);
-    for (int c = 0; c < 7; ++c) ex = fmax(ex, fabs(ff[c] - fl[c]) / (a * sc[c]));
-    return ex;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) ex = fmax(ex, fabs(ff[c] - fl[c]) * is[g[c]]);
+    return ex / a;
 }
 
 // Training data: features, weight deviation and flux excess of n sampled
@@ -321,7 +452,7 @@ __global__ __launch_bounds__(64) void router_sample_kernel(const T *__restrict__
     __syncthreads();
     if (!ok) return;
     float x[48];
-    sw::router_features<T>(sq, 64 * 6, t * 6, 1, x);
+    router_features<T>(sq, 64 * 6, t * 6, 1, x);
     for (int k = 0; k < 48; ++k) X[s * 48 + k] = x[k];
     T ff[7], fl[7], dv = T(0);
     sw::face_flux<T, true>(sq, 64 * 6, t * 6, 1, P.gamma, P.igm1, (T)P.eps, ff, &dv);
@@ -330,24 +461,31 @@ __global__ __launch_bounds__(64) void router_sample_kernel(const T *__restrict__
     ex_out[s] = (float)flux_excess<T>(sq, 64 * 6, t * 6, 1, ff, fl);
 }
 
-// Learned sweep (FP32 state): one tile of 256 interfaces as in the plain
-// sweep (FT = 4); features -> MLP on MFMA -> routing; the block compacts
-// its troubled and smooth interfaces into two lists so that full
-// characteristic WENO and the linear flux each run on packed waves.
+// Routed sweep (FP32 state): one tile of 256 interfaces as in the plain
+// sweep (FT = 4).  Features -> MLP on MFMA -> the interfaces called smooth
+// take the linear flux here; the troubled ones are appended to a queue that
+// troubled_kernel serves with full characteristic WENO in packed waves, so a
+// few troubled interfaces in a tile cost a few queue slots, not a wave.
+// force = -1: every interface smooth, the network not evaluated.  reuse:
+// take the decisions stored in mask (one byte per face, 1 = troubled) by an
+// earlier evaluation instead of evaluating the network; otherwise store them.
+// Queue entries pack the face position (x+1, y+1, z+1) in 21 bits each.
 template <int DIR>
-__global__ __launch_bounds__(256) void learned_sweep_kernel(const float *__restrict__ u,
-                                                            float *__restrict__ flux, Geom G,
-                                                            FaceBox F, Phys P,
-                                                            const float *__restrict__ th,
-                                                            float thr, int force,
-                                                            int32_t *__restrict__ nsmooth)
+__global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restrict__ u,
+                                                           float *__restrict__ flux, Geom G,
+                                                           FaceBox F, Phys P,
+                                                           const char *__restrict__ pk,
+                                                           float thr, int force,
+                                                           int32_t *__restrict__ nsmooth,
+                                                           unsigned long long *__restrict__ queue,
+                                                           int32_t *__restrict__ qcount,
+                                                           unsigned char *__restrict__ mask, int reuse)
 {
     constexpr int FT = 4;
     constexpr int NC = sw::tile_cells<DIR, FT>();
     __shared__ float sq[sw::NQ * NC];
-    __shared__ short xs[256 * XS];
-    __shared__ unsigned short tl[256], sl[256];
-    __shared__ int wcnt[8];
+    __shared__ __align__(16) short xs[4 * 32 * XS];     // 32 feature rows per wave
+    __shared__ int wcnt[4], qbase;
     constexpr int N = DIR;
     const int cm[8] = { 0, 1 + N, 1 + (N + 1) % 3, 1 + (N + 2) % 3, 4 + N, 4 + (N + 1) % 3,
                         4 + (N + 2) % 3, 7 };
@@ -380,77 +518,131 @@ __global__ __launch_bounds__(256) void learned_sweep_kernel(const float *__restr
         }
     }
     __syncthreads();
-    // --- interface t = 64*w + lane of the tile: position, activity, LDS offset
-    auto where = [&](int t, int (&pos)[3], int &off, int &cstr) -> bool {
-        const int ln = t & 63, ww = t >> 6;
+    // --- this thread's interface: position, activity, LDS offset
+    int pos[3], off, cstr;
+    bool act;
+    if constexpr (DIR == 0) {
+        const int nrows = F.cnt[1] * F.cnt[2];
+        const int row = ta * sw::ROWS + w;
+        pos[0] = tb * sw::TILE + lane;
+        pos[1] = F.lo[1] + row % F.cnt[1];
+        pos[2] = F.lo[2] + row / F.cnt[1];
+        off = w * sw::NCX + lane;
+        cstr = 1;
+        act = row < nrows && pos[0] < F.cnt[0];
+    } else {
+        constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
+        const int npos = F.cnt[A] * F.cnt[B];
+        const int p = ta * 64 + lane;
+        pos[A] = F.lo[A] + p % F.cnt[A];
+        pos[B] = F.lo[B] + p / F.cnt[A];
+        pos[N] = tb * FT + w;
+        off = w * 64 + lane;
+        cstr = 64;
+        act = p < npos && pos[N] < F.cnt[N];
+    }
+    // --- features and the MLP
+    bool troubled = false;
+    if (force == 0 && reuse) {
+        troubled = act && mask[F.idx(pos[0], pos[1], pos[2])] != 0;
+    } else if (force == 0) {
+        bf4 xf[12];
+        {
+            float x[48];
+            if (act) router_features<float>(sq, NC, off, cstr, x);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                xf[k] = act ? pack_bf4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]) : bf4{ 0, 0, 0, 0 };
+        }
+        MlpRegs R;
+        load_mlp_packed(pk, R);
+        short *g = xs + w * 32 * XS;
+        float lg = 0.f;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // the 32 lanes of groups 2h, 2h+1 put their features in the wave's rows
+            if ((lane >> 5) == h) {
+                bf4 *row = (bf4 *)(g + (lane & 31) * XS);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) row[k] = xf[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const float z0 = mlp_group(g, R, nullptr, nullptr, 0);
+            const float z1 = mlp_group(g + 16 * XS, R, nullptr, nullptr, 0);
+            if ((lane >> 4) == 2 * h) lg = z0;
+            if ((lane >> 4) == 2 * h + 1) lg = z1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        troubled = !(lg <= thr);                // NaN features count as troubled
+        if (act) mask[F.idx(pos[0], pos[1], pos[2])] = troubled ? 1 : 0;
+    }
+    // --- troubled interfaces: one queue reservation per block
+    const unsigned long long bt = __ballot(act && troubled);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) wcnt[w] = __popcll(bt);
+    __syncthreads();
+    const int ntr = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    if (tid == 0) {
+        int nact = 0;
         if constexpr (DIR == 0) {
             const int nrows = F.cnt[1] * F.cnt[2];
-            const int row = ta * sw::ROWS + ww;
-            pos[0] = tb * sw::TILE + ln;
-            pos[1] = F.lo[1] + row % F.cnt[1];
-            pos[2] = F.lo[2] + row / F.cnt[1];
-            off = ww * sw::NCX + ln;
-            cstr = 1;
-            return row < nrows && pos[0] < F.cnt[0];
+            const int rows = min(sw::ROWS, nrows - ta * sw::ROWS);
+            nact = rows * min(sw::TILE, F.cnt[0] - tb * sw::TILE);
         } else {
-            constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
-            const int npos = F.cnt[A] * F.cnt[B];
-            const int p = ta * 64 + ln;
-            pos[A] = F.lo[A] + p % F.cnt[A];
-            pos[B] = F.lo[B] + p / F.cnt[A];
-            pos[N] = tb * FT + ww;
-            off = ww * 64 + ln;
-            cstr = 64;
-            return p < npos && pos[N] < F.cnt[N];
+            const int npos = F.cnt[0] * F.cnt[DIR == 1 ? 2 : 1];
+            nact = min(64, npos - ta * 64) * min(FT, F.cnt[N] - tb * FT);
         }
-    };
-    int pos[3], off, cstr;
-    const bool act = where(tid, pos, off, cstr);
-    // --- features and the MLP
-    {
-        float x[48];
-        if (act) sw::router_features<float>(sq, NC, off, cstr, x);
-#pragma unroll
-        for (int k = 0; k < 48; ++k) xs[tid * XS + k] = act ? f2bf(x[k]) : (short)0;
+        if (nsmooth) nsmooth[(long)blockIdx.y * gridDim.x + blockIdx.x] = nact - ntr;
+        qbase = ntr > 0 ? atomicAdd(qcount, ntr) : 0;
     }
     __syncthreads();
-    bool troubled;
-    if (force != 0) {
-        troubled = force > 0;                 // routing switched off: all full / all linear
-    } else {
-        MlpRegs R;
-        load_mlp(th, R);
-        float lg[4];
-        mlp_wave(xs + w * 64 * XS, R, lg, nullptr, nullptr);
-        troubled = !(pick4(lg, lane >> 4) <= thr);      // NaN features count as troubled
+    if (act && troubled) {
+        int o = qbase;
+        for (int i = 0; i < w; ++i) o += wcnt[i];
+        o += __popcll(bt & below);
+        queue[o] = (unsigned long long)(pos[0] + 1) | ((unsigned long long)(pos[1] + 1) << 21) |
+                   ((unsigned long long)(pos[2] + 1) << 42);
     }
-    // --- compaction: troubled list tl, smooth list sl (block order)
-    const unsigned long long bt = __ballot(act && troubled), bs = __ballot(act && !troubled);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (lane == 0) { wcnt[w] = __popcll(bt); wcnt[4 + w] = __popcll(bs); }
-    __syncthreads();
-    int ot = 0, os = 0;
-    for (int i = 0; i < w; ++i) { ot += wcnt[i]; os += wcnt[4 + i]; }
-    const int ntr = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    const int nsm = wcnt[4] + wcnt[5] + wcnt[6] + wcnt[7];
-    if (act && troubled) tl[ot + __popcll(bt & below)] = (unsigned short)tid;
-    if (act && !troubled) sl[os + __popcll(bs & below)] = (unsigned short)tid;
-    __syncthreads();
-    if (tid == 0 && nsmooth) nsmooth[(long)blockIdx.y * gridDim.x + blockIdx.x] = nsm;
-    // --- fluxes on packed waves
-    for (int k = tid; k < ntr; k += 256) {
-        int p2[3], o2, c2;
-        where(tl[k], p2, o2, c2);
+    if (act && !troubled) {
         float out[7];
-        sw::face_flux<float>(sq, NC, o2, c2, P.gamma, P.igm1, (float)P.eps, out);
-        sw::store_face<N, float>(flux, F, p2, out);
+        sw::linear_flux<float>(sq, NC, off, cstr, out);
+        sw::store_face<N, float>(flux, F, pos, out);
     }
-    for (int k = tid; k < nsm; k += 256) {
-        int p2[3], o2, c2;
-        where(sl[k], p2, o2, c2);
+}
+
+// Full characteristic WENO at the queued troubled interfaces: each thread
+// stages its own six cells and computes one flux; blocks stride over the
+// queue, whose length the routed sweep left in *qcount.
+template <int DIR>
+__global__ __launch_bounds__(128) void troubled_kernel(const float *__restrict__ u,
+                                                       float *__restrict__ flux, Geom G, FaceBox F,
+                                                       Phys P,
+                                                       const unsigned long long *__restrict__ queue,
+                                                       const int32_t *__restrict__ qcount)
+{
+    __shared__ float sq[sw::NQ * 128 * 6];
+    constexpr int N = DIR;
+    const int cm[8] = { 0, 1 + N, 1 + (N + 1) % 3, 1 + (N + 2) % 3, 4 + N, 4 + (N + 1) % 3,
+                        4 + (N + 2) % 3, 7 };
+    const int t = threadIdx.x;
+    const long n = *qcount;
+    for (long e = (long)blockIdx.x * 128 + t; e - t < n; e += (long)gridDim.x * 128) {
+        if (e >= n) continue;
+        const unsigned long long q = queue[e];
+        int pos[3] = { (int)(q & 0x1fffff) - 1, (int)((q >> 21) & 0x1fffff) - 1, (int)(q >> 42) - 1 };
+        for (int j = 0; j < 6; ++j) {
+            int c[3] = { pos[0], pos[1], pos[2] };
+            c[N] = pos[N] - 3 + j;
+            const long id = G.base + c[0] * G.s[0] + c[1] * G.s[1] + (long)c[2] * G.s[2];
+            sw::stage_cell(u, id, G.sv, cm, P.gamma, sq + t * 6 + j, 128 * 6);
+        }
         float out[7];
-        sw::linear_flux<float>(sq, NC, o2, c2, out);
-        sw::store_face<N, float>(flux, F, p2, out);
+        sw::face_flux<float>(sq, 128 * 6, t * 6, 1, P.gamma, P.igm1, (float)P.eps, out);
+        sw::store_face<N, float>(flux, F, pos, out);
     }
 }
 
@@ -503,7 +695,13 @@ template hipError_t launch_router_sample<float>(const float *, const Geom &, con
                                                 const int32_t *, int, float *, float *, float *,
                                                 hipStream_t);
 
-long learned_sweep_blocks(int dir, const FaceBox &F)
+hipError_t launch_pack_mlp(const float *th, char *pk, hipStream_t st)
+{
+    hipLaunchKernelGGL(rt::pack_mlp_kernel, dim3(1), dim3(64), 0, st, th, pk);
+    return hipGetLastError();
+}
+
+long routed_sweep_blocks(int dir, const FaceBox &F)
 {
     long na, nb;
     if (dir == 0) sw::sweep_tiles<0, 4>(F, na, nb);
@@ -512,27 +710,37 @@ long learned_sweep_blocks(int dir, const FaceBox &F)
     return na * nb;
 }
 
-hipError_t launch_learned_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
-                                const Phys &P, const float *th, float thr, int force,
-                                int32_t *nsmooth, hipStream_t st)
+hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
+                              const Phys &P, const char *pk, float thr, int force, int32_t *nsmooth,
+                              unsigned long long *queue, int32_t *qcount, unsigned char *mask, int reuse,
+                              hipStream_t st)
 {
+    hipError_t e = hipMemsetAsync(qcount, 0, sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
     long na, nb;
     dim3 blk(64, 4);
+    const dim3 qgrid(2048), qblk(128);
     switch (dir) {
     case 0:
         sw::sweep_tiles<0, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::learned_sweep_kernel<0>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, th, thr, force, nsmooth);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<0>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
+                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        if (force == 0)
+            hipLaunchKernelGGL(rt::troubled_kernel<0>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
         break;
     case 1:
         sw::sweep_tiles<1, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::learned_sweep_kernel<1>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, th, thr, force, nsmooth);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<1>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
+                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        if (force == 0)
+            hipLaunchKernelGGL(rt::troubled_kernel<1>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
         break;
     default:
         sw::sweep_tiles<2, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::learned_sweep_kernel<2>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, th, thr, force, nsmooth);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<2>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
+                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        if (force == 0)
+            hipLaunchKernelGGL(rt::troubled_kernel<2>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
         break;
     }
     return hipGetLastError();

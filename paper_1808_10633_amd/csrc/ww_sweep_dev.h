@@ -362,65 +362,6 @@ __device__ __forceinline__ void linear_flux(const T *__restrict__ sq, int qs, in
     }
 }
 
-// Router features of one interface from its six staged cells (i-2..i+3),
-// six per sweep-frame conserved variable v, stored x[v*6 + j], all of the
-// form L(y) = 1 + log10(y / S_v + 1e-8) / 4:
-//   j = 0  largest first difference max |q_{m+1} - q_m|;
-//   j = 1  the jump across the interface |q_3 - q_2|;
-//   j = 2..5  largest |second|, |third|, |fourth| and the |fifth| difference.
-// The scales are those of the flux-excess label: with a = max(|v_n| + c_f)
-// on the stencil, S = max rho (mass), max(|m| + rho a) (momenta),
-// max(|B| + sqrt(rho) a) (fields), max E (energy).  On smooth data the
-// m-th difference falls like (kh)^m, so smoothness and amplitude are both
-// differences of O(1) features, which BF16 carries; the raw stencil values
-// would need ~20 bits to show a fifth difference.
-template <typename T>
-__device__ __forceinline__ void router_features(const T *__restrict__ sq, int qs, int off, int cstr,
-                                                float (&x)[48])
-{
-#define QF(q, j) sq[(q) * qs + off + (j) * cstr]
-    T a = T(0);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) a = fmax(a, fabs(QF(1, j) * QF(9, j)) + QF(10, j));
-    T sr = T(0), sm = T(0), sb = T(0), se = T(0);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const T r = QF(0, j);
-        const T m = sqrt(QF(1, j) * QF(1, j) + QF(2, j) * QF(2, j) + QF(3, j) * QF(3, j));
-        const T b = sqrt(QF(4, j) * QF(4, j) + QF(5, j) * QF(5, j) + QF(6, j) * QF(6, j));
-        sr = fmax(sr, r);
-        sm = fmax(sm, m + r * a);
-        sb = fmax(sb, b + sqrt(r) * a);
-        se = fmax(se, QF(7, j));
-    }
-    const T isr = T(1) / sr, ism = T(1) / sm, isb = T(1) / sb, ise = T(1) / se;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const T is = v == 0 ? isr : v < 4 ? ism : v < 7 ? isb : ise;
-        T d[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) d[j] = QF(v, j);
-        T y[6];
-        y[1] = fabs(d[3] - d[2]);
-#pragma unroll
-        for (int m = 1; m <= 5; ++m) {           // d <- its next difference
-            T mx = T(0);
-#pragma unroll
-            for (int j = 0; j + m < 6; ++j) { d[j] = d[j + 1] - d[j]; mx = fmax(mx, fabs(d[j])); }
-            y[m == 1 ? 0 : m] = mx;
-        }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const T z = y[j] * is + T(1e-8);
-            if constexpr (sizeof(T) == 4)
-                x[v * 6 + j] = 1.0f + 0.0752574989f * __log2f(z);          // log10(2) / 4
-            else
-                x[v * 6 + j] = (float)(T(1) + T(0.25) * log10(z));
-        }
-    }
-#undef QF
-}
-
 // Store a sweep-frame interface flux in grid components:
 // rho, mx, my, mz, B_(N+1), B_(N+2), E.
 template <int N, typename T>

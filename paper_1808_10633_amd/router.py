@@ -25,7 +25,7 @@ import numpy as np
 
 from . import wombat
 
-LABEL_THRESHOLD = 1e-4
+LABEL_THRESHOLD = 1e-3
 NIN, NH = 48, 32
 
 

@@ -159,6 +159,129 @@ def test_learned_sweep_forced_routes():
     assert err < 2e-6
 
 
+def test_routed_sweep_matches_its_two_routes():
+    # the routed sweep (mode 0) with a network that calls everything troubled
+    # (all interfaces through the queue and the full-WENO pass) must equal
+    # the plain FP32 sweep bitwise; calling everything smooth must equal the
+    # all-linear mode bitwise; a mixed routing must equal one of the two at
+    # every cell whose neighbourhood is routed one way
+    n = 24
+    u = I.turbulence((n, n, n), mach=2.0, beta=5.0, seed=63, kmax=6).numpy().copy()
+    theta = R.init_params(7)
+    _, plain = _fp32_ctx_rhs(n, u)
+    _, lin = _fp32_ctx_rhs(n, u, theta, mode=-1)
+    hi = theta.clone()
+    hi[-1] = 1e4
+    ctx, r1 = _fp32_ctx_rhs(n, u, hi, mode=0)
+    assert ctx.router_stats()[0] == 0
+    # the queued pass and the plain sweep are separately compiled kernels of
+    # the same FP32 face arithmetic: equal up to FMA contraction choices
+    g = O.Grid(n, n, n, 1 / n, 1 / n, 1 / n)
+    e1, _ = scaled_rhs_error(g.interior(r1.double().cpu().numpy()), g.interior(plain.double().cpu().numpy()),
+                             g.interior(u), 1 / n)
+    say(f"[routed sweep] all troubled (queued full WENO) vs plain FP32 sweep: {e1:.2e}")
+    assert e1 < 1e-6
+    lo = theta.clone()
+    lo[-1] = -1e4
+    ctx, r0 = _fp32_ctx_rhs(n, u, lo, mode=0)
+    sm, tot, _ = ctx.router_stats()
+    assert sm == tot and torch.equal(r0, lin)
+    # mixed: half of the box uniform (every feature of its interfaces equal,
+    # hence one logit z0, routed one way), the threshold at the median logit
+    # of the other interfaces, so the turbulent half is mixed
+    ctx = W.Context(n, n, n, precision=W.WW_FP32_MIXED)
+    u2 = u.copy()
+    u2[:, 3:n + 3, 3:n + 3, 3:3 + n // 2] = u[:, 3:n + 3, 3:n + 3, 3:3 + n // 2].mean(axis=(1, 2, 3))[:, None, None, None]
+    ug = torch.from_numpy(u2).cuda().float()
+    _, plain = _fp32_ctx_rhs(n, u2)
+    _, lin = _fp32_ctx_rhs(n, u2, theta, mode=-1)
+    faces = []
+    for d in range(3):
+        lim = [n + (d == a) for a in range(3)]
+        g = torch.stack(torch.meshgrid(*[torch.arange(m) for m in lim], indexing="ij"), -1).reshape(-1, 3)
+        faces.append(torch.cat([torch.full((len(g), 1), d), g], 1))
+    where = torch.cat(faces).to(torch.int32).cuda().contiguous()
+    X, _, _ = ctx.router_sample(ug, where)
+    z = W.mlp_forward(theta, X).cpu()
+    wh = where.cpu().long()
+    inner = (wh[:, 1] >= 3) & (wh[:, 1] <= n // 2 - 3)              # stencils inside the uniform half
+    z0 = float(z[inner].max())
+    assert float(z[inner].min()) == z0
+    tl = float(z[~inner].median())             # splits the turbulent half
+    if abs(tl - z0) < 0.01:
+        tl = z0 + 0.02
+    ctx.set_router(theta, 1.0 / (1.0 + math.exp(-tl)), 0)
+    mix = torch.zeros_like(ug)
+    ctx.rhs(ug, mix)
+    torch.cuda.synchronize()
+    sm, tot, _ = ctx.router_stats()
+    say(f"[routed sweep] mixed routing: {sm}/{tot} smooth")
+    assert 0 < sm < tot
+    # per cell (periodic box): may any face touching it, or one of its 26
+    # neighbours (CT reaches that far), go the other way?  Faces within 1e-4
+    # of the threshold count as both.
+    anyt = torch.zeros((n,) * 3, dtype=torch.bool)
+    anys = torch.zeros((n,) * 3, dtype=torch.bool)
+    for flag, grid in ((z > tl - 1e-4, anyt), (z < tl + 1e-4, anys)):
+        sel = wh[flag]
+        c = sel[:, 1:] % n                                  # face i sits between cells i-1 and i
+        grid[c[:, 0], c[:, 1], c[:, 2]] = True
+        c2 = sel[:, 1:].clone()
+        c2[torch.arange(len(c2)), sel[:, 0]] -= 1
+        c2 %= n
+        grid[c2[:, 0], c2[:, 1], c2[:, 2]] = True
+    def pool(g):
+        gp = torch.nn.functional.pad(g[None, None].float(), (1, 1, 1, 1, 1, 1), mode="circular")
+        return torch.nn.functional.max_pool3d(gp, 3, 1, 0)[0, 0] > 0
+    full_only = ~pool(anys)
+    lin_only = ~pool(anyt)
+    sl = I.interior_slices(n, n, n)
+    m, p_, l_ = mix[sl].cpu(), plain[sl].cpu(), lin[sl].cpu()
+    fo = full_only.permute(2, 1, 0)                      # (x, y, z) -> (z, y, x)
+    lo_ = lin_only.permute(2, 1, 0)
+    say(f"  cells routed all-full {int(fo.sum())}, all-linear {int(lo_.sum())}")
+    assert int(lo_.sum()) + int(fo.sum()) > 0
+    assert torch.equal(m[:, lo_], l_[:, lo_])
+    scale = p_.abs().amax(dim=(1, 2, 3), keepdim=True)[:, :, 0, 0]
+    d = ((m[:, fo] - p_[:, fo]).abs() / scale).max() if int(fo.sum()) else torch.tensor(0.0)
+    say(f"  full-only cells vs plain: {float(d):.2e} of each variable's largest |rhs|")
+    assert float(d) < 1e-5
+
+
+def test_routed_step_reuses_first_stage_decisions():
+    # a step evaluates the network at its first stage and reuses those
+    # decisions for the other three: with a network that calls everything
+    # troubled (smooth) the step equals the plain (all-linear) step
+    n = 20
+    u = I.turbulence((n, n, n), mach=1.0, beta=10.0, seed=64, kmax=5).float().cuda().contiguous()
+    theta = R.init_params(9)
+    ref = W.Context(n, n, n, precision=W.WW_FP32_MIXED)
+    dt = ref.cfl_dt(u)
+    up = u.clone()
+    ref.step(up, dt)
+    hi = theta.clone()
+    hi[-1] = 1e4
+    ctx = W.Context(n, n, n, precision=W.WW_FP32_MIXED)
+    ctx.set_router(hi, 0.5, 0)
+    ut = u.clone()
+    ctx.step(ut, dt)
+    g = O.Grid(n, n, n, 1 / n, 1 / n, 1 / n)
+    S = np.abs(g.interior(up.double().cpu().numpy())).reshape(8, -1).max(1)
+    e = float((np.abs(g.interior((ut - up).double().cpu().numpy())).reshape(8, -1).max(1) / np.maximum(S, 1e-30)).max())
+    say(f"[routed step] all troubled vs plain step: {e:.2e}")
+    assert e < 1e-6 and ctx.router_stats()[2] == 0
+    lo = theta.clone()
+    lo[-1] = -1e4
+    ctx.set_router(lo, 0.5, -1)
+    ul = u.clone()
+    ctx.step(ul, dt)
+    ctx.set_router(lo, 0.5, 0)
+    ur = u.clone()
+    ctx.step(ur, dt)
+    torch.cuda.synchronize()
+    assert ctx.router_stats()[2] == 0 and torch.equal(ur, ul)
+
+
 def blast_tube(n):
     """1-D periodic tube, pressure 100 on the left half and 0.01 on the right,
     rho = 1, at rest, no field: the linear flux drives the pressure negative
@@ -211,7 +334,7 @@ def shocked_state(n, seed, steps, kmax=8.0):
 def test_router_trained_on_shocked_state():
     n = 256
     say("[router] training on a shocked 256^3 state")
-    ctx, u = shocked_state(n, 5001, 50)
+    ctx, u = shocked_state(n, 5001, 100)
     X, dev, ex, t = R.sample(ctx, u, 120000, seed=7)
     frac = float(t.mean())
     say(f"  troubled fraction {frac:.3f}")

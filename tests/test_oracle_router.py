@@ -1,6 +1,8 @@
 """Pins of the oracle parts behind the learned router: the weight deviation,
 the flux-excess label, the linear component-wise flux, the stencil features and the MLP
 gradient (against finite differences, not against its own formulas)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -82,13 +84,28 @@ def test_fast_speed_matches_c_oracle(orc):
         assert abs(mlp.fast_speed(U) - orc.wave_speeds(U, 0)[0]) < 1e-13 * orc.wave_speeds(U, 0)[0]
 
 
+def mitchell(z):
+    # log2 z ~ (e - 1) + (2 f - 1) for z = f 2^e, f in [1/2, 1)
+    f, e = math.frexp(z)
+    return (e - 1) + (2 * f - 1)
+
+
+def test_mitchell_log2():
+    assert all(mlp.log2m(2.0 ** k) == k for k in range(-30, 30))
+    z = np.exp(np.linspace(-20, 20, 5001))
+    err = np.log2(z) - mlp.log2m(z)
+    assert err.min() > -1e-6 and err.max() < 0.0861
+    assert np.allclose(mlp.log2m(z), [mitchell(float(np.float32(v))) for v in z], atol=1e-12)
+
+
 def test_features_definition(orc):
     W0 = np.array([1.0, 0.5, 0.2, -0.1, 0.3, 0.2, 0.1, 1.0])
     U0 = orc.prim_to_cons(W0)
-    L = lambda y, S: 1 + 0.25 * np.log10(y / S + 1e-8)
-    # uniform stencil: every difference is 0 -> L(0) = 1 + log10(1e-8)/4 = -1
+    L = lambda y, S: 1 + 0.25 * math.log10(2.0) * mitchell(float(np.float32(y / S + 1e-8)))
+    L0 = L(0.0, 1.0)
+    # uniform stencil: every difference is 0 -> L(0)
     x = mlp.features(np.tile(U0, (6, 1))).reshape(8, 6)
-    assert np.allclose(x, -1.0, atol=1e-15)
+    assert np.allclose(x, L0, atol=1e-15)
     # only rho alternates 1, 1.1, 1, ...: |differences| 0.1, 0.2, 0.4, 0.8,
     # 1.6, interface jump 0.1; mass scale max rho = 1.1
     st = np.tile(U0, (6, 1))
@@ -96,12 +113,12 @@ def test_features_definition(orc):
     x = mlp.features(st).reshape(8, 6)
     assert np.allclose(x[0], [L(0.1, 1.1), L(0.1, 1.1), L(0.2, 1.1), L(0.4, 1.1), L(0.8, 1.1), L(1.6, 1.1)],
                        atol=1e-12)
-    assert np.allclose(x[1:], -1.0, atol=1e-15)
+    assert np.allclose(x[1:], L0, atol=1e-15)
     # energy quadratic in the cell index: third and higher differences vanish
     st = np.tile(U0, (6, 1))
     st[:, 7] = U0[7] + 0.125 * np.arange(6) ** 2
     x = mlp.features(st).reshape(8, 6)[7]
-    assert np.allclose(x[3:], -1.0, atol=1e-12) and x[2] > x[3] + 1
+    assert np.allclose(x[3:], L0, atol=1e-7) and x[2] > x[3] + 1
     # a resolved sine (kh = 2 pi / 64): the fifth difference sits ~(kh)^4,
     # i.e. ~4 decades (one feature unit), below the first
     lam = 64
@@ -114,7 +131,7 @@ def test_features_definition(orc):
         st = np.array([orc.prim_to_cons(W0 * (1 + 0.3 * rng.normal(size=8)) * [1, 1, 1, 1, 1, 1, 1, 0] +
                                         [0, 0, 0, 0, 0, 0, 0, 1]) for _ in range(6)])
         x = mlp.features(st)
-        assert np.all(np.isfinite(x)) and x.min() >= -1.0
+        assert np.all(np.isfinite(x)) and x.min() >= L0
 
 
 def test_mlp_gradient_matches_finite_differences():
