@@ -13,10 +13,26 @@ __global__ __launch_bounds__(256) void sweep_kernel(const T *__restrict__ u, T *
     sw::sweep_tile<DIR, FT, T>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void sweep_xseg_kernel(const T *__restrict__ u, T *__restrict__ flux,
+                                                         Geom G, FaceBox F, Phys P)
+{
+    __shared__ T sq[sw::NQ * sw::ROWS * sw::NCX];
+    sw::sweep_tile_xseg<T>(u, flux, G, F, P, blockIdx.x, sq);
+}
+
 template <int DIR, int FT, typename T>
 hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
                       hipStream_t st)
 {
+    if (DIR == 0 && F.cnt[0] >= sw::XSEG_MIN) {
+        // long rows: flattened face segments, no ragged tile per row
+        const long total = (long)F.cnt[0] * F.cnt[1] * F.cnt[2];
+        const long nt = (total + sw::TILE * sw::ROWS - 1) / (sw::TILE * sw::ROWS);
+        hipLaunchKernelGGL((sweep_xseg_kernel<T>), dim3((unsigned)nt), dim3(sw::TILE, sw::ROWS), 0, st,
+                           u, flux, G, F, P);
+        return hipGetLastError();
+    }
     long na, nb;
     sw::sweep_tiles<DIR, FT>(F, na, nb);
     hipLaunchKernelGGL((sweep_kernel<DIR, FT, T>), dim3((unsigned)na, (unsigned)nb),

@@ -506,6 +506,62 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
     __syncthreads();
 }
 
+// x sweep over the flattened (row, face) space, for rows of at least
+// XSEG_MIN faces: tile t takes the TILE*ROWS consecutive faces t*256 ..
+// of the row-major face sequence, which touch at most 4 rows; for each row
+// it stages the cells of its face segment with the 3 + 2 halo (256 + 5*4
+// cells at most, the size of the regular x tile) and each thread computes
+// one face.  Only the last tile of the sweep is ragged.
+constexpr int XSEG_MIN = 86;
+template <typename T>
+__device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__restrict__ flux,
+                                                const Geom &G, const FaceBox &F, const Phys &P,
+                                                long tile, T *sq)
+{
+    const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
+    constexpr int NC = ROWS * NCX;
+    constexpr int TF = TILE * ROWS;
+    const long nf = F.cnt[0];
+    const long total = (long)F.cnt[1] * F.cnt[2] * nf;
+    const long g0 = tile * TF;
+    const long g1 = (g0 + TF - 1 < total - 1) ? g0 + TF - 1 : total - 1;
+    const long r_lo = g0 / nf;
+    const int nseg = (int)(g1 / nf - r_lo) + 1;      // <= 4 since nf >= XSEG_MIN
+    int fa[4], off[5];
+    off[0] = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int a = s == 0 ? (int)(g0 - r_lo * nf) : 0;
+        const int b = s == nseg - 1 ? (int)(g1 - (r_lo + s) * nf) : (int)nf - 1;
+        fa[s] = a;
+        off[s + 1] = off[s] + (s < nseg ? b - a + 6 : 0);
+    }
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    for (int c = tid; c < off[nseg]; c += TF) {
+        int s = 0;
+        while (s < 3 && c >= off[s + 1]) ++s;
+        const long row = r_lo + s;
+        const int x = fa[s] - 3 + (c - off[s]);
+        const int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
+        const long id = G.base + x * G.s[0] + j * G.s[1] + (long)k * G.s[2];
+        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+    }
+    __syncthreads();
+    const long g = g0 + tid;
+    if (g <= g1) {
+        const long row = g / nf;
+        const int f = (int)(g - row * nf), s = (int)(row - r_lo);
+        int pos[3];
+        pos[0] = f;
+        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
+        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
+        T out[7];
+        // stencil cells f-3 .. f+2 sit at segment offset f - fa
+        face_flux<T>(sq, NC, off[s] + (f - fa[s]), 1, P.gamma, P.igm1, (T)P.eps, out);
+        store_face<0, T>(flux, F, pos, out);
+    }
+}
+
 // Number of tiles (ta, tb) of a sweep.
 template <int DIR, int FT>
 __host__ __device__ inline void sweep_tiles(const FaceBox &F, long &na, long &nb)

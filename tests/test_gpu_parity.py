@@ -42,6 +42,12 @@ def rhs_case(name):
     if name == "turb_67x10x9":
         g = O.Grid(67, 10, 9, 1 / 67, 1 / 67, 1 / 67)
         u = I.turbulence((67, 10, 9), mach=1.0, beta=1.0, seed=21, kmax=4, dx=1 / 67).numpy().copy()
+    elif name == "turb_100x7x6":       # x rows of 101 faces: flattened x segments, 4 rows per tile
+        g = O.Grid(100, 7, 6, 0.01, 0.01, 0.01)
+        u = I.turbulence((100, 7, 6), mach=1.0, beta=1.0, seed=22, kmax=4, dx=0.01).numpy().copy()
+    elif name == "smooth_85x5x4":      # 86 faces per x row: the smallest flattened-segment row
+        g = O.Grid(85, 5, 4, 1 / 85, 0.1, 0.1)
+        u = random_smooth(85, 5, 4, seed=10, amp=0.2)
     elif name == "smooth_13x70x11":
         g = O.Grid(13, 70, 11, 0.07, 0.011, 0.05)
         u = random_smooth(13, 70, 11, seed=3, amp=0.2)
@@ -87,7 +93,7 @@ def rhs_case(name):
     return g, u
 
 
-RHS_CASES = ["turb_67x10x9", "smooth_13x70x11", "smooth_9x8x71", "hydro_B0_16x12x10",
+RHS_CASES = ["turb_67x10x9", "turb_100x7x6", "smooth_85x5x4", "smooth_13x70x11", "smooth_9x8x71", "hydro_B0_16x12x10",
              "Bx_only_20x9x9", "triple_point_14x8x8", "brio_wu_1d", "sod_1d", "xy_2d",
              "xz_2d_outflow", "yz_2d"]
 
