@@ -21,10 +21,31 @@ __global__ __launch_bounds__(256) void sweep_xseg_kernel(const T *__restrict__ u
     sw::sweep_tile_xseg<T>(u, flux, G, F, P, blockIdx.x, sq);
 }
 
+// FP64 y/z sweeps: 32 positions x 8 faces per tile (1.6 staged cells per
+// face instead of 2.25 with 64 x 4, in 43 KB of LDS); measured 3 % faster at
+// 512^3.  FP32 keeps 64 positions x 8 faces (sweep_tile, FT = 8).
+constexpr int YZ_PW_F64 = 32;
+
+template <int DIR, int PW, typename T>
+__global__ __launch_bounds__(256) void sweep_yz_kernel(const T *__restrict__ u, T *__restrict__ flux,
+                                                       Geom G, FaceBox F, Phys P)
+{
+    __shared__ T sq[sw::NQ * sw::yz_cells<PW>()];
+    sw::sweep_tile_yz<DIR, PW, T>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
+}
+
 template <int DIR, int FT, typename T>
 hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
                       hipStream_t st)
 {
+    if (DIR != 0 && sizeof(T) == 8) {
+        constexpr int PW = YZ_PW_F64, B = (DIR == 1) ? 2 : 1;
+        const long npos = (long)F.cnt[0] * F.cnt[B];
+        const long na = (npos + PW - 1) / PW, nb = (F.cnt[DIR] + 256 / PW - 1) / (256 / PW);
+        hipLaunchKernelGGL((sweep_yz_kernel<DIR == 0 ? 1 : DIR, PW, T>), dim3((unsigned)na, (unsigned)nb),
+                           dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P);
+        return hipGetLastError();
+    }
     if (DIR == 0 && F.cnt[0] >= sw::XSEG_MIN) {
         // long rows: flattened face segments, no ragged tile per row
         const long total = (long)F.cnt[0] * F.cnt[1] * F.cnt[2];
@@ -40,7 +61,7 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
     return hipGetLastError();
 }
 
-// faces per y/z tile: 4 in FP64 (LDS-limited), 8 in FP32
+// faces per y/z tile of the FP32 sweep (FP64 y/z sweeps use sweep_yz_kernel)
 template <typename T> constexpr int ft_of() { return sizeof(T) == 8 ? 4 : 8; }
 
 }  // namespace

@@ -527,21 +527,29 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
     const long g1 = (g0 + TF - 1 < total - 1) ? g0 + TF - 1 : total - 1;
     const long r_lo = g0 / nf;
     const int nseg = (int)(g1 / nf - r_lo) + 1;      // <= 4 since nf >= XSEG_MIN
-    int fa[4], off[5];
-    off[0] = 0;
+    // segment s: faces fa_s.. of row r_lo + s, staged from sq offset o_s
+    // (kept in scalars: a dynamically indexed array would live in scratch)
+    int fa0 = 0, fa1 = 0, fa2 = 0, fa3 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0;
+    {
+        int o = 0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int a = s == 0 ? (int)(g0 - r_lo * nf) : 0;
-        const int b = s == nseg - 1 ? (int)(g1 - (r_lo + s) * nf) : (int)nf - 1;
-        fa[s] = a;
-        off[s + 1] = off[s] + (s < nseg ? b - a + 6 : 0);
+        for (int s = 0; s < 4; ++s) {
+            const int a = s == 0 ? (int)(g0 - r_lo * nf) : 0;
+            const int b = s == nseg - 1 ? (int)(g1 - (r_lo + s) * nf) : (int)nf - 1;
+            o += s < nseg ? b - a + 6 : 0;
+            if (s == 0) { fa0 = a; o1 = o; }
+            if (s == 1) { fa1 = a; o2 = o; }
+            if (s == 2) { fa2 = a; o3 = o; }
+            if (s == 3) { fa3 = a; o4 = o; }
+        }
     }
+    auto fa_of = [&](int s) { return s == 0 ? fa0 : s == 1 ? fa1 : s == 2 ? fa2 : fa3; };
+    auto off_of = [&](int s) { return s == 0 ? 0 : s == 1 ? o1 : s == 2 ? o2 : o3; };
     const int tid = threadIdx.x + TILE * threadIdx.y;
-    for (int c = tid; c < off[nseg]; c += TF) {
-        int s = 0;
-        while (s < 3 && c >= off[s + 1]) ++s;
+    for (int c = tid; c < o4; c += TF) {
+        const int s = (c >= o1) + (c >= o2) + (c >= o3);
         const long row = r_lo + s;
-        const int x = fa[s] - 3 + (c - off[s]);
+        const int x = fa_of(s) - 3 + (c - off_of(s));
         const int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
         const long id = G.base + x * G.s[0] + j * G.s[1] + (long)k * G.s[2];
         stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
@@ -557,8 +565,51 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
         pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
         T out[7];
         // stencil cells f-3 .. f+2 sit at segment offset f - fa
-        face_flux<T>(sq, NC, off[s] + (f - fa[s]), 1, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T>(sq, NC, off_of(s) + (f - fa_of(s)), 1, P.gamma, P.igm1, (T)P.eps, out);
         store_face<0, T>(flux, F, pos, out);
+    }
+}
+
+// y or z sweep with PW positions of the transverse plane (x fastest) per
+// tile and 256/PW faces along the sweep, one face per thread: fewer
+// positions per tile stage fewer halo cells per face ((FT+5)/FT) in the
+// same LDS.  Used by the single-box sweeps.
+template <int PW>
+__host__ __device__ constexpr int yz_cells() { return PW * (256 / PW + 5); }
+
+template <int DIR, int PW, typename T>
+__device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__restrict__ flux,
+                                              const Geom &G, const FaceBox &F, const Phys &P,
+                                              int ta, int tb, T *sq)
+{
+    constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+    constexpr int FTY = 256 / PW, NC = yz_cells<PW>();
+    constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
+    const int cm[8] = { 0, 1 + N, 1 + T1, 1 + T2, 4 + N, 4 + T1, 4 + T2, 7 };
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    const int nlast = G.n[N] + 2;
+    const int npos = F.cnt[A] * F.cnt[B];
+    const int f0 = tb * FTY;
+    for (int c = tid; c < NC; c += 256) {
+        const int rr = c / PW, pc = c - rr * PW;
+        const int p = ta * PW + pc, y = f0 - 3 + rr;
+        if (p < npos && y <= nlast) {
+            const int ca = F.lo[A] + p % F.cnt[A], cb = F.lo[B] + p / F.cnt[A];
+            const long id = G.base + ca * G.s[A] + cb * G.s[B] + (long)y * G.s[N];
+            stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+        }
+    }
+    __syncthreads();
+    const int fr = tid / PW, pl = tid - fr * PW;
+    const int p = ta * PW + pl;
+    int pos[3];
+    pos[A] = F.lo[A] + p % F.cnt[A];
+    pos[B] = F.lo[B] + p / F.cnt[A];
+    pos[N] = f0 + fr;
+    if (p < npos && pos[N] < F.cnt[N]) {
+        T out[7];
+        face_flux<T>(sq, NC, fr * PW + pl, PW, P.gamma, P.igm1, (T)P.eps, out);
+        store_face<N, T>(flux, F, pos, out);
     }
 }
 
