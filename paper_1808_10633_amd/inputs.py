@@ -306,3 +306,29 @@ def turbulence(dims, mach, beta, seed, *, dx=None, gamma=GAMMA, rho0=1.0, p0=1.0
     out = torch.zeros(padded_shape(nx, ny, nz), dtype=torch.float64, device=device)
     out[interior_slices(nx, ny, nz)] = u
     return out.to(dtype)
+
+
+def field_loop(n, gamma=GAMMA, amp=1e-3, radius=0.3, v=(2.0, 1.0)):
+    """Field-loop advection (the magnetic-energy test of Sec. 3.1): a 2n x n
+    periodic box [-1, 1] x [-1/2, 1/2], rho = 1, p = 1, uniform velocity v
+    (after t = 1 the loop is back where it started), and a weak loop from
+    the potential A_z = amp (radius - r) inside r < radius.  A_z is sampled
+    at cell corners; the face fields are its discrete curl and the cell
+    field their two-face mean, so the corner divergence of the cell field
+    vanishes.  Returns a padded numpy array (8, 1, n + 6, 2n + 6)."""
+    nx, ny = 2 * n, n
+    dx = 2.0 / nx
+    dy = 1.0 / ny
+    xc = -1.0 + dx * np.arange(nx + 1)           # corners
+    yc = -0.5 + dy * np.arange(ny + 1)
+    X, Y = np.meshgrid(xc, yc, indexing="xy")     # (ny+1, nx+1)
+    r = np.sqrt(X ** 2 + Y ** 2)
+    A = np.where(r < radius, amp * (radius - r), 0.0)
+    bx_face = (A[1:, :] - A[:-1, :]) / dy          # at (x corners, y centres): (ny, nx+1)
+    by_face = -(A[:, 1:] - A[:, :-1]) / dx         # at (x centres, y corners): (ny+1, nx)
+    bx = 0.5 * (bx_face[:, 1:] + bx_face[:, :-1])  # (ny, nx)
+    by = 0.5 * (by_face[1:, :] + by_face[:-1, :])
+    rho = np.ones((ny, nx))
+    z = np.zeros((ny, nx))
+    U = conserved(rho, [z + v[0], z + v[1], z], [bx, by, z], np.ones((ny, nx)), gamma)
+    return _pad(U[:, None, :, :], nx, ny, 1)
