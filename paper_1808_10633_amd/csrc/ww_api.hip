@@ -630,9 +630,12 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
     if (!ctx->queue) {
         long most = 1, all = 1;
         for (int d = 0; d < 3; ++d)
-            if (ctx->G.act[d]) { most = std::max(most, ctx->F[d].sc); all += ctx->F[d].sc; }
+            if (ctx->G.act[d]) {
+                most = std::max(most, ww::ROUTED_QUEUE_REGIONS * ww::routed_queue_capacity(d, ctx->F[d]));
+                all += ctx->F[d].sc;
+            }
         if (dev_alloc((void **)&ctx->queue, sizeof(unsigned long long) * most) != hipSuccess ||
-            dev_alloc((void **)&ctx->qcount, sizeof(int32_t)) != hipSuccess ||
+            dev_alloc((void **)&ctx->qcount, sizeof(int32_t) * ww::ROUTED_QUEUE_REGIONS) != hipSuccess ||
             dev_alloc((void **)&ctx->rmask, all) != hipSuccess) {
             if (ctx->queue) (void)hipFree(ctx->queue);
             if (ctx->qcount) (void)hipFree(ctx->qcount);

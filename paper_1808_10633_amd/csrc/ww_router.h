@@ -19,9 +19,14 @@ hipError_t launch_router_sample(const T *u, const Geom &G, const Phys &P, const 
 constexpr int MLP_PACKED_BYTES = 10 * 64 * 8 + 25 * 64 * 4;
 hipError_t launch_pack_mlp(const float *th, char *pk, hipStream_t st);
 long routed_sweep_blocks(int dir, const FaceBox &F);
+// Troubled-queue entries the routed sweep of direction dir may need: 64
+// regions of ceil(blocks / 64) * 256 entries; qcount holds 64 counters.
+long routed_queue_capacity(int dir, const FaceBox &F);
+constexpr int ROUTED_QUEUE_REGIONS = 64;
 // Routed sweep of direction dir (force 0 routed, -1 all linear), then the
-// full-WENO pass over the queued troubled interfaces.  queue holds at least
-// F.sc entries; *qcount is cleared on st first.  mask (F.sc bytes) receives
+// full-WENO pass over the queued troubled interfaces.  queue holds
+// 64 * routed_queue_capacity(dir, F) entries; the 64 counters in qcount are
+// cleared on st first.  mask (F.sc bytes) receives
 // the decisions, or supplies them when reuse is set.
 hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
                               const Phys &P, const char *pk, float thr, int force, int32_t *nsmooth,

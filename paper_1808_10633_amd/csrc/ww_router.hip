@@ -23,6 +23,9 @@ namespace rt {
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+constexpr int YZ_PW = 32;         // positions per y/z tile of the routed sweep (8 faces each)
+constexpr int QREG = 64;          // troubled-queue regions (atomic counters)
+static_assert(QREG == ROUTED_QUEUE_REGIONS, "queue regions");
 constexpr int OW1 = 0, OB1 = 1536, OW2 = 1568, OB2 = 2592, OW3 = 2624, OB3 = 2656;
 constexpr int XS = 52;     // LDS row stride (BF16 elements) of the feature matrix
 
@@ -461,11 +464,14 @@ __global__ __launch_bounds__(64) void router_sample_kernel(const T *__restrict__
     ex_out[s] = (float)flux_excess<T>(sq, 64 * 6, t * 6, 1, ff, fl);
 }
 
-// Routed sweep (FP32 state): one tile of 256 interfaces as in the plain
-// sweep (FT = 4).  Features -> MLP on MFMA -> the interfaces called smooth
+// Routed sweep (FP32 state): one tile of 256 interfaces, one per thread.
+// Features -> MLP on MFMA -> the interfaces called smooth
 // take the linear flux here; the troubled ones are appended to a queue that
 // troubled_kernel serves with full characteristic WENO in packed waves, so a
 // few troubled interfaces in a tile cost a few queue slots, not a wave.
+// The queue is split into QREG regions (block b appends to region b % QREG,
+// of capacity qcap entries) so that the one atomic reservation per block
+// spreads over QREG counters instead of contending on one.
 // force = -1: every interface smooth, the network not evaluated.  reuse:
 // take the decisions stored in mask (one byte per face, 1 = troubled) by an
 // earlier evaluation instead of evaluating the network; otherwise store them.
@@ -478,68 +484,53 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
                                                            float thr, int force,
                                                            int32_t *__restrict__ nsmooth,
                                                            unsigned long long *__restrict__ queue,
-                                                           int32_t *__restrict__ qcount,
+                                                           int32_t *__restrict__ qcount, long qcap,
                                                            unsigned char *__restrict__ mask, int reuse)
 {
-    constexpr int FT = 4;
-    constexpr int NC = sw::tile_cells<DIR, FT>();
+    // tiles as the plain sweeps: x in flattened 256-face segments (rows of
+    // XSEG_MIN faces or more) or 4 rows x 64 faces; y/z 32 positions x 8 faces
+    constexpr int NC = DIR == 0 ? sw::XSEG_CELLS : sw::yz_cells<YZ_PW>();
     __shared__ float sq[sw::NQ * NC];
     __shared__ __align__(16) short xs[4 * 32 * XS];     // 32 feature rows per wave
-    __shared__ int wcnt[4], qbase;
+    __shared__ int wcnt[4], wact[4];
+    __shared__ long qbase;
     constexpr int N = DIR;
-    const int cm[8] = { 0, 1 + N, 1 + (N + 1) % 3, 1 + (N + 2) % 3, 4 + N, 4 + (N + 1) % 3,
-                        4 + (N + 2) % 3, 7 };
     const int lane = threadIdx.x, w = threadIdx.y, tid = lane + 64 * w;
-    const int ta = blockIdx.x, tb = blockIdx.y;
-    const int nlast = G.n[N] + 2;
-    // --- stage the tile (as sw::sweep_tile)
-    if constexpr (DIR == 0) {
-        const int nrows = F.cnt[1] * F.cnt[2];
-        for (int c = tid; c < sw::ROWS * sw::NCX; c += 256) {
-            int rr = c / sw::NCX, xi = c - rr * sw::NCX;
-            int row = ta * sw::ROWS + rr, x = tb * sw::TILE - 3 + xi;
-            if (row < nrows && x <= nlast) {
-                int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
-                long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
-                sw::stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
-            }
-        }
-    } else {
-        constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
-        const int npos = F.cnt[A] * F.cnt[B];
-        const int p = ta * 64 + lane;
-        const int ca = F.lo[A] + p % F.cnt[A], cb = F.lo[B] + p / F.cnt[A];
-        for (int rr = w; rr < FT + 5; rr += 4) {
-            int y = tb * FT - 3 + rr;
-            if (p < npos && y <= nlast) {
-                long id = G.base + ca * G.s[A] + cb * G.s[B] + (long)y * G.s[N];
-                sw::stage_cell(u, id, G.sv, cm, P.gamma, sq + rr * 64 + lane, NC);
-            }
-        }
-    }
-    __syncthreads();
-    // --- this thread's interface: position, activity, LDS offset
     int pos[3], off, cstr;
     bool act;
     if constexpr (DIR == 0) {
-        const int nrows = F.cnt[1] * F.cnt[2];
-        const int row = ta * sw::ROWS + w;
-        pos[0] = tb * sw::TILE + lane;
-        pos[1] = F.lo[1] + row % F.cnt[1];
-        pos[2] = F.lo[2] + row / F.cnt[1];
-        off = w * sw::NCX + lane;
         cstr = 1;
-        act = row < nrows && pos[0] < F.cnt[0];
+        if (F.cnt[0] >= sw::XSEG_MIN) {
+            const sw::XSeg X = sw::xseg_setup(F, blockIdx.x);
+            sw::xseg_stage<float>(u, G, F, P, X, sq);
+            __syncthreads();
+            act = sw::xseg_face(F, X, tid, pos, off);
+        } else {
+            const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
+            const int ta = blockIdx.x, tb = blockIdx.y, nlast = G.n[0] + 2;
+            const int nrows = F.cnt[1] * F.cnt[2];
+            for (int c = tid; c < sw::ROWS * sw::NCX; c += 256) {
+                int rr = c / sw::NCX, xi = c - rr * sw::NCX;
+                int row = ta * sw::ROWS + rr, x = tb * sw::TILE - 3 + xi;
+                if (row < nrows && x <= nlast) {
+                    int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
+                    long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
+                    sw::stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+                }
+            }
+            __syncthreads();
+            const int row = ta * sw::ROWS + w;
+            pos[0] = tb * sw::TILE + lane;
+            pos[1] = F.lo[1] + row % F.cnt[1];
+            pos[2] = F.lo[2] + row / F.cnt[1];
+            off = w * sw::NCX + lane;
+            act = row < nrows && pos[0] < F.cnt[0];
+        }
     } else {
-        constexpr int A = 0, B = (DIR == 1) ? 2 : 1;
-        const int npos = F.cnt[A] * F.cnt[B];
-        const int p = ta * 64 + lane;
-        pos[A] = F.lo[A] + p % F.cnt[A];
-        pos[B] = F.lo[B] + p / F.cnt[A];
-        pos[N] = tb * FT + w;
-        off = w * 64 + lane;
-        cstr = 64;
-        act = p < npos && pos[N] < F.cnt[N];
+        cstr = YZ_PW;
+        sw::yz_stage<DIR, YZ_PW, float>(u, G, F, P, blockIdx.x, blockIdx.y, sq);
+        __syncthreads();
+        act = sw::yz_face<DIR, YZ_PW>(F, blockIdx.x, blockIdx.y, tid, pos, off);
     }
     // --- features and the MLP
     bool troubled = false;
@@ -581,27 +572,21 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         if (act) mask[F.idx(pos[0], pos[1], pos[2])] = troubled ? 1 : 0;
     }
     // --- troubled interfaces: one queue reservation per block
-    const unsigned long long bt = __ballot(act && troubled);
+    const unsigned long long bt = __ballot(act && troubled), ba = __ballot(act);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (lane == 0) wcnt[w] = __popcll(bt);
+    if (lane == 0) { wcnt[w] = __popcll(bt); wact[w] = __popcll(ba); }
     __syncthreads();
     const int ntr = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     if (tid == 0) {
-        int nact = 0;
-        if constexpr (DIR == 0) {
-            const int nrows = F.cnt[1] * F.cnt[2];
-            const int rows = min(sw::ROWS, nrows - ta * sw::ROWS);
-            nact = rows * min(sw::TILE, F.cnt[0] - tb * sw::TILE);
-        } else {
-            const int npos = F.cnt[0] * F.cnt[DIR == 1 ? 2 : 1];
-            nact = min(64, npos - ta * 64) * min(FT, F.cnt[N] - tb * FT);
-        }
+        const int nact = wact[0] + wact[1] + wact[2] + wact[3];
         if (nsmooth) nsmooth[(long)blockIdx.y * gridDim.x + blockIdx.x] = nact - ntr;
-        qbase = ntr > 0 ? atomicAdd(qcount, ntr) : 0;
+        const long b = (long)blockIdx.y * gridDim.x + blockIdx.x;
+        const int reg = (int)(b % QREG);
+        qbase = ntr > 0 ? (long)reg * qcap + atomicAdd(qcount + reg, ntr) : 0;
     }
     __syncthreads();
     if (act && troubled) {
-        int o = qbase;
+        long o = qbase;
         for (int i = 0; i < w; ++i) o += wcnt[i];
         o += __popcll(bt & below);
         queue[o] = (unsigned long long)(pos[0] + 1) | ((unsigned long long)(pos[1] + 1) << 21) |
@@ -615,24 +600,26 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
 }
 
 // Full characteristic WENO at the queued troubled interfaces: each thread
-// stages its own six cells and computes one flux; blocks stride over the
-// queue, whose length the routed sweep left in *qcount.
+// stages its own six cells and computes one flux; blockIdx.y is the queue
+// region, whose length the routed sweep left in qcount[region], and the
+// blocks of a region stride over it.
 template <int DIR>
 __global__ __launch_bounds__(128) void troubled_kernel(const float *__restrict__ u,
                                                        float *__restrict__ flux, Geom G, FaceBox F,
                                                        Phys P,
                                                        const unsigned long long *__restrict__ queue,
-                                                       const int32_t *__restrict__ qcount)
+                                                       const int32_t *__restrict__ qcount, long qcap)
 {
     __shared__ float sq[sw::NQ * 128 * 6];
     constexpr int N = DIR;
     const int cm[8] = { 0, 1 + N, 1 + (N + 1) % 3, 1 + (N + 2) % 3, 4 + N, 4 + (N + 1) % 3,
                         4 + (N + 2) % 3, 7 };
     const int t = threadIdx.x;
-    const long n = *qcount;
+    const long n = qcount[blockIdx.y];
+    const unsigned long long *qr = queue + blockIdx.y * qcap;
     for (long e = (long)blockIdx.x * 128 + t; e - t < n; e += (long)gridDim.x * 128) {
         if (e >= n) continue;
-        const unsigned long long q = queue[e];
+        const unsigned long long q = qr[e];
         int pos[3] = { (int)(q & 0x1fffff) - 1, (int)((q >> 21) & 0x1fffff) - 1, (int)(q >> 42) - 1 };
         for (int j = 0; j < 6; ++j) {
             int c[3] = { pos[0], pos[1], pos[2] };
@@ -701,13 +688,34 @@ hipError_t launch_pack_mlp(const float *th, char *pk, hipStream_t st)
     return hipGetLastError();
 }
 
+// Grid of the routed sweep of direction dir.
+static void routed_grid(int dir, const FaceBox &F, long &na, long &nb)
+{
+    if (dir == 0) {
+        if (F.cnt[0] >= sw::XSEG_MIN) {
+            const long total = (long)F.cnt[0] * F.cnt[1] * F.cnt[2];
+            na = (total + 255) / 256;
+            nb = 1;
+        } else {
+            sw::sweep_tiles<0, 4>(F, na, nb);
+        }
+    } else {
+        const long npos = (long)F.cnt[0] * F.cnt[dir == 1 ? 2 : 1];
+        na = (npos + rt::YZ_PW - 1) / rt::YZ_PW;
+        nb = (F.cnt[dir] + 256 / rt::YZ_PW - 1) / (256 / rt::YZ_PW);
+    }
+}
+
 long routed_sweep_blocks(int dir, const FaceBox &F)
 {
     long na, nb;
-    if (dir == 0) sw::sweep_tiles<0, 4>(F, na, nb);
-    else if (dir == 1) sw::sweep_tiles<1, 4>(F, na, nb);
-    else sw::sweep_tiles<2, 4>(F, na, nb);
+    routed_grid(dir, F, na, nb);
     return na * nb;
+}
+
+long routed_queue_capacity(int dir, const FaceBox &F)
+{
+    return (routed_sweep_blocks(dir, F) + rt::QREG - 1) / rt::QREG * 256;
 }
 
 hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
@@ -715,32 +723,30 @@ hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom 
                               unsigned long long *queue, int32_t *qcount, unsigned char *mask, int reuse,
                               hipStream_t st)
 {
-    hipError_t e = hipMemsetAsync(qcount, 0, sizeof(int32_t), st);
+    hipError_t e = hipMemsetAsync(qcount, 0, sizeof(int32_t) * rt::QREG, st);
     if (e != hipSuccess) return e;
     long na, nb;
-    dim3 blk(64, 4);
-    const dim3 qgrid(2048), qblk(128);
+    routed_grid(dir, F, na, nb);
+    const long cap = routed_queue_capacity(dir, F);
+    const dim3 grid((unsigned)na, (unsigned)nb), blk(64, 4), qgrid(32, rt::QREG), qblk(128);
     switch (dir) {
     case 0:
-        sw::sweep_tiles<0, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<0>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<0>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
+                           nsmooth, queue, qcount, cap, mask, reuse);
         if (force == 0)
-            hipLaunchKernelGGL(rt::troubled_kernel<0>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
+            hipLaunchKernelGGL(rt::troubled_kernel<0>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
         break;
     case 1:
-        sw::sweep_tiles<1, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<1>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<1>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
+                           nsmooth, queue, qcount, cap, mask, reuse);
         if (force == 0)
-            hipLaunchKernelGGL(rt::troubled_kernel<1>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
+            hipLaunchKernelGGL(rt::troubled_kernel<1>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
         break;
     default:
-        sw::sweep_tiles<2, 4>(F, na, nb);
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<2>, dim3((unsigned)na, (unsigned)nb), blk, 0, st, u,
-                           flux, G, F, P, pk, thr, force, nsmooth, queue, qcount, mask, reuse);
+        hipLaunchKernelGGL(rt::routed_sweep_kernel<2>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
+                           nsmooth, queue, qcount, cap, mask, reuse);
         if (force == 0)
-            hipLaunchKernelGGL(rt::troubled_kernel<2>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount);
+            hipLaunchKernelGGL(rt::troubled_kernel<2>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
         break;
     }
     return hipGetLastError();

@@ -510,62 +510,97 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
 // XSEG_MIN faces: tile t takes the TILE*ROWS consecutive faces t*256 ..
 // of the row-major face sequence, which touch at most 4 rows; for each row
 // it stages the cells of its face segment with the 3 + 2 halo (256 + 5*4
-// cells at most, the size of the regular x tile) and each thread computes
-// one face.  Only the last tile of the sweep is ragged.
+// cells at most, the size of the regular x tile) and each thread takes one
+// face.  Only the last tile of the sweep is ragged.
 constexpr int XSEG_MIN = 86;
+constexpr int XSEG_CELLS = ROWS * NCX;
+
+// Segment table of one tile: segment s = faces fa_s.. of row r_lo + s at
+// transverse cell (j_s, k_s), staged from LDS offset o_s, holding tile-local
+// faces from b_s on.  Kept in scalars (a dynamically indexed array would
+// live in scratch), and the row -> (j, k) divisions are done once per
+// segment, not per cell.
+struct XSeg {
+    long g0;
+    int nf, nface, fa0, fa1, fa2, fa3, o1, o2, o3, o4, b1, b2, b3;
+    int j0, j1, j2, j3, k0, k1, k2, k3;
+    __device__ int fa(int s) const { return s == 0 ? fa0 : s == 1 ? fa1 : s == 2 ? fa2 : fa3; }
+    __device__ int off(int s) const { return s == 0 ? 0 : s == 1 ? o1 : s == 2 ? o2 : o3; }
+    __device__ int bs(int s) const { return s == 0 ? 0 : s == 1 ? b1 : s == 2 ? b2 : b3; }
+    __device__ int j(int s) const { return s == 0 ? j0 : s == 1 ? j1 : s == 2 ? j2 : j3; }
+    __device__ int k(int s) const { return s == 0 ? k0 : s == 1 ? k1 : s == 2 ? k2 : k3; }
+};
+
+__device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile)
+{
+    constexpr int TF = TILE * ROWS;
+    XSeg X;
+    X.nf = F.cnt[0];
+    const long total = (long)F.cnt[1] * F.cnt[2] * X.nf;
+    X.g0 = tile * TF;
+    const long g1 = (X.g0 + TF - 1 < total - 1) ? X.g0 + TF - 1 : total - 1;
+    X.nface = (int)(g1 - X.g0 + 1);
+    const long r_lo = X.g0 / X.nf;
+    const int nseg = (int)(g1 / X.nf - r_lo) + 1;      // <= 4 since nf >= XSEG_MIN
+    X.fa0 = X.fa1 = X.fa2 = X.fa3 = X.o1 = X.o2 = X.o3 = X.o4 = X.b1 = X.b2 = X.b3 = 0;
+    X.j0 = X.j1 = X.j2 = X.j3 = X.k0 = X.k1 = X.k2 = X.k3 = 0;
+    int o = 0, bsum = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int a = s == 0 ? (int)(X.g0 - r_lo * X.nf) : 0;
+        const int b = s == nseg - 1 ? (int)(g1 - (r_lo + s) * X.nf) : X.nf - 1;
+        const long row = r_lo + s;
+        const int jj = F.lo[1] + (int)(row % F.cnt[1]), kk = F.lo[2] + (int)(row / F.cnt[1]);
+        o += s < nseg ? b - a + 6 : 0;
+        bsum += s < nseg ? b - a + 1 : 0;                // faces of segments 0..s
+        if (s == 0) { X.fa0 = a; X.o1 = o; X.b1 = bsum; X.j0 = jj; X.k0 = kk; }
+        if (s == 1) { X.fa1 = a; X.o2 = o; X.b2 = bsum; X.j1 = jj; X.k1 = kk; }
+        if (s == 2) { X.fa2 = a; X.o3 = o; X.b3 = bsum; X.j2 = jj; X.k2 = kk; }
+        if (s == 3) { X.fa3 = a; X.o4 = o; X.j3 = jj; X.k3 = kk; }
+    }
+    return X;
+}
+
+// Stage the tile's cells (x sweep frame), sq with stride XSEG_CELLS.
+template <typename T>
+__device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F,
+                                           const Phys &P, const XSeg &X, T *sq)
+{
+    const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    for (int c = tid; c < X.o4; c += TILE * ROWS) {
+        const int s = (c >= X.o1) + (c >= X.o2) + (c >= X.o3);
+        const int x = X.fa(s) - 3 + (c - X.off(s));
+        const long id = G.base + x * G.s[0] + X.j(s) * G.s[1] + (long)X.k(s) * G.s[2];
+        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XSEG_CELLS);
+    }
+}
+
+// Face of thread tid: position and LDS offset of its cell i-2 (stride 1).
+__device__ __forceinline__ bool xseg_face(const FaceBox &F, const XSeg &X, int tid, int (&pos)[3], int &off)
+{
+    const int t = tid < X.nface ? tid : X.nface - 1;
+    const int s = (t >= X.b1) + (t >= X.b2) + (t >= X.b3);
+    const int f = X.fa(s) + (t - X.bs(s));
+    pos[0] = f;
+    pos[1] = X.j(s);
+    pos[2] = X.k(s);
+    off = X.off(s) + (f - X.fa(s));      // stencil cells f-3 .. f+2 from segment offset f - fa
+    return tid < X.nface;
+}
+
 template <typename T>
 __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__restrict__ flux,
                                                 const Geom &G, const FaceBox &F, const Phys &P,
                                                 long tile, T *sq)
 {
-    const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
-    constexpr int NC = ROWS * NCX;
-    constexpr int TF = TILE * ROWS;
-    const long nf = F.cnt[0];
-    const long total = (long)F.cnt[1] * F.cnt[2] * nf;
-    const long g0 = tile * TF;
-    const long g1 = (g0 + TF - 1 < total - 1) ? g0 + TF - 1 : total - 1;
-    const long r_lo = g0 / nf;
-    const int nseg = (int)(g1 / nf - r_lo) + 1;      // <= 4 since nf >= XSEG_MIN
-    // segment s: faces fa_s.. of row r_lo + s, staged from sq offset o_s
-    // (kept in scalars: a dynamically indexed array would live in scratch)
-    int fa0 = 0, fa1 = 0, fa2 = 0, fa3 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0;
-    {
-        int o = 0;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int a = s == 0 ? (int)(g0 - r_lo * nf) : 0;
-            const int b = s == nseg - 1 ? (int)(g1 - (r_lo + s) * nf) : (int)nf - 1;
-            o += s < nseg ? b - a + 6 : 0;
-            if (s == 0) { fa0 = a; o1 = o; }
-            if (s == 1) { fa1 = a; o2 = o; }
-            if (s == 2) { fa2 = a; o3 = o; }
-            if (s == 3) { fa3 = a; o4 = o; }
-        }
-    }
-    auto fa_of = [&](int s) { return s == 0 ? fa0 : s == 1 ? fa1 : s == 2 ? fa2 : fa3; };
-    auto off_of = [&](int s) { return s == 0 ? 0 : s == 1 ? o1 : s == 2 ? o2 : o3; };
-    const int tid = threadIdx.x + TILE * threadIdx.y;
-    for (int c = tid; c < o4; c += TF) {
-        const int s = (c >= o1) + (c >= o2) + (c >= o3);
-        const long row = r_lo + s;
-        const int x = fa_of(s) - 3 + (c - off_of(s));
-        const int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
-        const long id = G.base + x * G.s[0] + j * G.s[1] + (long)k * G.s[2];
-        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
-    }
+    const XSeg X = xseg_setup(F, tile);
+    xseg_stage<T>(u, G, F, P, X, sq);
     __syncthreads();
-    const long g = g0 + tid;
-    if (g <= g1) {
-        const long row = g / nf;
-        const int f = (int)(g - row * nf), s = (int)(row - r_lo);
-        int pos[3];
-        pos[0] = f;
-        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
-        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
+    int pos[3], off;
+    if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        // stencil cells f-3 .. f+2 sit at segment offset f - fa
-        face_flux<T>(sq, NC, off_of(s) + (f - fa_of(s)), 1, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out);
         store_face<0, T>(flux, F, pos, out);
     }
 }
@@ -573,14 +608,13 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
 // y or z sweep with PW positions of the transverse plane (x fastest) per
 // tile and 256/PW faces along the sweep, one face per thread: fewer
 // positions per tile stage fewer halo cells per face ((FT+5)/FT) in the
-// same LDS.  Used by the single-box sweeps.
+// same LDS.
 template <int PW>
 __host__ __device__ constexpr int yz_cells() { return PW * (256 / PW + 5); }
 
 template <int DIR, int PW, typename T>
-__device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__restrict__ flux,
-                                              const Geom &G, const FaceBox &F, const Phys &P,
-                                              int ta, int tb, T *sq)
+__device__ __forceinline__ void yz_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F,
+                                         const Phys &P, int ta, int tb, T *sq)
 {
     constexpr int N = DIR, T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
     constexpr int FTY = 256 / PW, NC = yz_cells<PW>();
@@ -599,17 +633,35 @@ __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__rest
             stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
         }
     }
-    __syncthreads();
+}
+
+// Face of thread tid: position and LDS offset of its cell i-2 (stride PW).
+template <int DIR, int PW>
+__device__ __forceinline__ bool yz_face(const FaceBox &F, int ta, int tb, int tid, int (&pos)[3], int &off)
+{
+    constexpr int FTY = 256 / PW, N = DIR, A = 0, B = (DIR == 1) ? 2 : 1;
+    const int npos = F.cnt[A] * F.cnt[B];
     const int fr = tid / PW, pl = tid - fr * PW;
     const int p = ta * PW + pl;
-    int pos[3];
     pos[A] = F.lo[A] + p % F.cnt[A];
     pos[B] = F.lo[B] + p / F.cnt[A];
-    pos[N] = f0 + fr;
-    if (p < npos && pos[N] < F.cnt[N]) {
+    pos[N] = tb * FTY + fr;
+    off = fr * PW + pl;
+    return p < npos && pos[N] < F.cnt[N];
+}
+
+template <int DIR, int PW, typename T>
+__device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__restrict__ flux,
+                                              const Geom &G, const FaceBox &F, const Phys &P,
+                                              int ta, int tb, T *sq)
+{
+    yz_stage<DIR, PW, T>(u, G, F, P, ta, tb, sq);
+    __syncthreads();
+    int pos[3], off;
+    if (yz_face<DIR, PW>(F, ta, tb, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T>(sq, NC, fr * PW + pl, PW, P.gamma, P.igm1, (T)P.eps, out);
-        store_face<N, T>(flux, F, pos, out);
+        face_flux<T>(sq, yz_cells<PW>(), off, PW, P.gamma, P.igm1, (T)P.eps, out);
+        store_face<DIR, T>(flux, F, pos, out);
     }
 }
 
