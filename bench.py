@@ -183,7 +183,8 @@ def learned_form(a, wombat, inputs, router):
     the pre-steps scaled to the same physical time (pre * train_n / n steps),
     interfaces sampled at random (features and flux-excess labels from the
     library), MLP trained by the library's BF16 MFMA kernels, threshold set
-    for <= 2 % false-smooth on the training set.  Evaluation: seed 5000 at
+    for <= 10 % false-smooth on the training set (the interfaces it routes
+    smooth stay at flux excess ~1e-3: reported).  Evaluation: seed 5000 at
     learned_n^3 after pre steps; from that snapshot `learned_steps` steps of
     full WENO and of the learned route (the full run's step sizes replayed),
     compared to each other, and the all-linear route (no network) as the
@@ -213,7 +214,7 @@ def learned_form(a, wombat, inputs, router):
                                log_every=max(a.train_steps // 10, 1))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    thr = router.choose_threshold(theta, Xtr, ttr, max_false_smooth=0.02)
+    thr = router.choose_threshold(theta, Xtr, ttr, max_false_smooth=0.10)
     val = router.evaluate(theta, Xva, tva, thr)
     print(f"[bench] learned: trained in {train_s:.1f} s, loss {hist[0][1]:.3f} -> {hist[-1][1]:.3f}, "
           f"threshold {thr:.3g}", file=sys.stderr, flush=True)
@@ -222,10 +223,10 @@ def learned_form(a, wombat, inputs, router):
     n = a.learned_n
     for _, ctx, u in shocked_turbulence(n, 5000, wombat, inputs, a.pre_steps):
         pass
-    Xe, deve, _, te = router.sample(ctx, u, 250000, seed=50000)
-    ev = router.evaluate(theta, Xe, te, thr)
+    Xe, deve, exe, te = router.sample(ctx, u, 250000, seed=50000)
+    ev = router.evaluate(theta, Xe, te, thr, excess=exe)
     ev["weight_deviation_above_1e-2"] = float((deve > 1e-2).float().mean())
-    del Xe, te, deve
+    del Xe, te, deve, exe
     snap = u.clone()
     sl = inputs.interior_slices(n, n, n)
     nsteps = a.learned_steps

@@ -88,20 +88,29 @@ def train(X, t, steps=2000, batch=4096, lr=2e-3, seed=0, pos_weight=None, log_ev
     return theta, hist
 
 
-def evaluate(theta, X, t, threshold=0.5):
-    """Classifier statistics at a probability threshold."""
+def evaluate(theta, X, t, threshold=0.5, excess=None):
+    """Classifier statistics at a probability threshold; with the flux
+    excess of the samples, also the largest and 99.9th-percentile excess
+    among the interfaces it would route to the linear flux."""
+    import torch
     z = wombat.mlp_forward(theta, X)
     pred = (z > math.log(threshold / (1.0 - threshold))).float()
     tr = t > 0.5
     n_tr = int(tr.sum())
     false_smooth = int(((pred < 0.5) & tr).sum())
-    return {"accuracy": float((pred == t).float().mean()),
-            "troubled_fraction": float(t.mean()),
-            "predicted_troubled_fraction": float(pred.mean()),
-            "false_smooth_rate": false_smooth / max(n_tr, 1)}
+    out = {"accuracy": float((pred == t).float().mean()),
+           "troubled_fraction": float(t.mean()),
+           "predicted_troubled_fraction": float(pred.mean()),
+           "false_smooth_rate": false_smooth / max(n_tr, 1)}
+    if excess is not None:
+        es = excess[pred < 0.5].float()
+        if es.numel():
+            out["routed_smooth_excess_max"] = float(es.max())
+            out["routed_smooth_excess_p999"] = float(torch.quantile(es[:1 << 24], 0.999))
+    return out
 
 
-def choose_threshold(theta, X, t, max_false_smooth=0.02):
+def choose_threshold(theta, X, t, max_false_smooth=0.10):
     """Largest threshold whose false-smooth rate (troubled interfaces sent
     to the linear flux) stays at or below max_false_smooth."""
     z = wombat.mlp_forward(theta, X).double().cpu().numpy()
