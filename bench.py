@@ -32,7 +32,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
 # and ww_internal.h).
 MEASURED_TRAFFIC = {
-    ("7490f409550ccfca", "fp64", 512): {"read": 24.04e9, "write": 7.83e9,
+    ("48a95e5ba7fec6f5", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
+                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
+    ("48a95e5ba7fec6f5", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
 

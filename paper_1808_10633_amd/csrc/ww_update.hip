@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a)
     up::update_cell(a, pos);
 }
 
-constexpr int MX_TX = 64, MX_TY = 4, MX_KZ = 32;   // march tile: x lanes, y rows, z cells
+constexpr int MX_TX = 64, MX_TY = 4, MX_KZ = 16;   // march tile: x lanes, y rows, z cells
 constexpr int NXCD = 8;                              // MI355X: 8 XCDs, blocks dealt round-robin
 
 // Three active axes: one thread per (i, j) column segment of MX_KZ cells,
