@@ -204,8 +204,9 @@ typedef struct wombat_weno_batch wombat_weno_batch_t;
  * each edge 8..1024 cells.  From cfg only dx (the cell width of every
  * patch and axis), gamma, cfl, eps, precision, stream and device are used.
  * Allocates three work arenas, the face-flux scratch of up to 4 blocks per
- * CU, the patch table and the schedule (largest patch first onto the
- * least-loaded block).  *out is written only on success.
+ * CU, the patch table and the patch order (largest first; in each stage the
+ * resident blocks take the next patch of that order from a shared counter
+ * until none is left).  *out is written only on success.
  * Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP, WW_ERR_UNSUPPORTED. */
 int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int32_t *dims,
                            wombat_weno_batch_t **out);

@@ -18,8 +18,9 @@ struct PatchDesc {
 template <typename T>
 struct BatchArgs {
     const PatchDesc *pd;
-    const int *sched_ptr;      // CSR schedule: block b owns sched_list[ptr[b] .. ptr[b+1])
-    const int *sched_list;
+    const int *order;          // patches by decreasing cost
+    int npatch;
+    int32_t *counter;          // next position in order (cleared before the stage)
     const T *u0;               // arena of the step's initial state
     T *us;                     // arena of the stage input (ghosts filled here)
     T *acc;                    // arena of the RK accumulator
@@ -41,5 +42,9 @@ hipError_t launch_batch_stage(const BatchArgs<T> &a, int ft, int nblocks, hipStr
 
 template <typename T>
 hipError_t batch_occupancy(int ft, int *blocks_per_cu);
+
+// Clear the n per-stage work counters of a step (a kernel, so that it can be
+// captured in a graph).
+hipError_t launch_batch_reset(int32_t *counters, int n, hipStream_t st);
 
 }  // namespace ww

@@ -1,6 +1,7 @@
-// ww_batch_api.hip -- C ABI of the batched form: arena layout, static
-// largest-first schedule of patches onto resident blocks, graph capture and
-// replay of whole RK4 steps, and the autotuner of the launch shape.
+// ww_batch_api.hip -- C ABI of the batched form: arena layout, the
+// largest-first patch order the resident blocks take their work from, graph
+// capture and replay of whole RK4 steps, and the autotuner of the launch
+// shape.
 #include "../../include/wombat_weno.h"
 #include "ww_batch.h"
 
@@ -33,7 +34,8 @@ struct wombat_weno_batch {
     int ft, bpc, nblocks;           // launch shape: faces per y/z tile, blocks per CU
     int maxblocks;
     PatchDesc *pd;
-    int *sched_ptr, *sched_list;
+    int *order;            // patches by decreasing cost
+    int32_t *counters;     // work counters of the 4 stages of a step
     void *work[3];                  // A, B, acc arenas
     void *scratch;
     double *dt;
@@ -126,34 +128,15 @@ double patch_cost(const int n[3])
     return c;
 }
 
-// Largest-first onto the least-loaded of nblocks slots; within a slot the
-// patches run in decreasing size.
-void make_schedule(const std::vector<int> &dims, int nblocks, std::vector<int> &ptr,
-                   std::vector<int> &list)
+// Patches by decreasing estimated cost (ties by index).
+void make_order(const std::vector<int> &dims, std::vector<int> &order)
 {
     const int np = (int)dims.size() / 3;
-    std::vector<int> order(np);
+    order.resize(np);
     std::iota(order.begin(), order.end(), 0);
     std::vector<double> cost(np);
     for (int p = 0; p < np; ++p) cost[p] = patch_cost(&dims[3 * p]);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    typedef std::pair<double, int> Slot;
-    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-    for (int b = 0; b < nblocks; ++b) heap.push(Slot(0.0, b));
-    std::vector<std::vector<int>> per(nblocks);
-    for (int p : order) {
-        Slot s = heap.top();
-        heap.pop();
-        per[s.second].push_back(p);
-        heap.push(Slot(s.first + cost[p], s.second));
-    }
-    ptr.assign(nblocks + 1, 0);
-    list.clear();
-    for (int b = 0; b < nblocks; ++b) {
-        ptr[b] = (int)list.size();
-        list.insert(list.end(), per[b].begin(), per[b].end());
-    }
-    ptr[nblocks] = (int)list.size();
 }
 
 int set_shape(wombat_weno_batch_t *b, int ft, int bpc)
@@ -164,13 +147,9 @@ int set_shape(wombat_weno_batch_t *b, int ft, int bpc)
     if (e != hipSuccess) return bhip(b, e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     if (occ < 1) return bfail(b, WW_ERR_UNSUPPORTED, "batched kernel does not fit on a CU");
     if (bpc > occ) bpc = occ;
-    WB_CHECK(b, hipStreamSynchronize(b->st));      // no launch may still read the schedule
+    WB_CHECK(b, hipStreamSynchronize(b->st));      // no launch may still run with the old shape
     int nblocks = bpc * b->ncu;
     if (nblocks > b->maxblocks) nblocks = b->maxblocks;
-    std::vector<int> ptr, list;
-    make_schedule(b->dims, nblocks, ptr, list);
-    WB_CHECK(b, hipMemcpy(b->sched_ptr, ptr.data(), sizeof(int) * ptr.size(), hipMemcpyHostToDevice));
-    WB_CHECK(b, hipMemcpy(b->sched_list, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice));
     b->ft = ft;
     b->bpc = bpc;
     b->nblocks = nblocks;
@@ -188,11 +167,13 @@ int launch_step_t(wombat_weno_batch_t *b, T *u, hipStream_t st)
     T *A = (T *)b->work[0], *B = (T *)b->work[1], *acc = (T *)b->work[2];
     T *in[4] = { u, A, B, A };
     T *out[4] = { A, B, A, u };
+    WB_CHECK(b, ww::launch_batch_reset(b->counters, 4, st));
     for (int s = 0; s < 4; ++s) {
         BatchArgs<T> a;
         a.pd = b->pd;
-        a.sched_ptr = b->sched_ptr;
-        a.sched_list = b->sched_list;
+        a.order = b->order;
+        a.npatch = (int)(b->dims.size() / 3);
+        a.counter = b->counters + s;
         a.u0 = u;
         a.us = in[s];
         a.acc = acc;
@@ -231,8 +212,8 @@ void release(wombat_weno_batch_t *b)
     for (int i = 0; i < 3; ++i) if (b->work[i]) (void)hipFree(b->work[i]);
     if (b->scratch) (void)hipFree(b->scratch);
     if (b->pd) (void)hipFree(b->pd);
-    if (b->sched_ptr) (void)hipFree(b->sched_ptr);
-    if (b->sched_list) (void)hipFree(b->sched_list);
+    if (b->order) (void)hipFree(b->order);
+    if (b->counters) (void)hipFree(b->counters);
     if (b->dt) (void)hipFree(b->dt);
     if (b->flag) (void)hipFree(b->flag);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -333,11 +314,14 @@ int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int3
         if (hipMalloc(&b->work[i], b->esize * b->arena) != hipSuccess) { b->work[i] = nullptr; return fail_oom("work arenas"); }
     if (hipMalloc(&b->scratch, b->esize * b->slot_elems * b->maxblocks) != hipSuccess) { b->scratch = nullptr; return fail_oom("face scratch"); }
     if (hipMalloc((void **)&b->pd, sizeof(PatchDesc) * npatch) != hipSuccess) { b->pd = nullptr; return fail_oom("patch table"); }
-    if (hipMalloc((void **)&b->sched_ptr, sizeof(int) * (b->maxblocks + 1)) != hipSuccess) { b->sched_ptr = nullptr; return fail_oom("schedule"); }
-    if (hipMalloc((void **)&b->sched_list, sizeof(int) * npatch) != hipSuccess) { b->sched_list = nullptr; return fail_oom("schedule"); }
+    if (hipMalloc((void **)&b->order, sizeof(int) * npatch) != hipSuccess) { b->order = nullptr; return fail_oom("patch order"); }
+    if (hipMalloc((void **)&b->counters, sizeof(int32_t) * 4) != hipSuccess) { b->counters = nullptr; return fail_oom("work counters"); }
     if (hipMalloc((void **)&b->dt, sizeof(double) * npatch) != hipSuccess) { b->dt = nullptr; return fail_oom("dt"); }
     if (hipMalloc((void **)&b->flag, sizeof(int32_t) * npatch) != hipSuccess) { b->flag = nullptr; return fail_oom("flags"); }
+    std::vector<int> order;
+    make_order(b->dims, order);
     if (hipMemcpy(b->pd, b->hpd.data(), sizeof(PatchDesc) * npatch, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order, order.data(), sizeof(int) * npatch, hipMemcpyHostToDevice) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess) {
         release(b);
