@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--batch-patches", type=int, default=4096,
                     help="patches of the batched form (0 skips it)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-router form")
+    ap.add_argument("--patch-sweep", action="store_true",
+                    help="only run the batched form at uniform patch sizes 8^3..64^3 (one JSON line)")
     ap.add_argument("--learned-n", type=int, default=512)
     ap.add_argument("--train-n", type=int, default=256)
     ap.add_argument("--pre-steps", type=int, default=200,
@@ -150,6 +152,41 @@ def batched_form(a, wombat, inputs, opcount):
                         "interfaces_per_launch": faces, "kernel_ms": stage_ms}}
     del bt, ar
     return res
+
+
+def patch_sweep(a, wombat, inputs):
+    """Batched form at uniform patch edges 8..64, about 2^26 interior zones
+    each (the GPU counterpart of a patch-size study): every patch holds the
+    same periodic turbulence realisation (rms Mach 1, beta 100), FP32,
+    autotuned launch shape, graph-replayed steps."""
+    import tempfile
+    import torch
+    rows = []
+    for e in (8, 12, 16, 24, 32, 48, 64):
+        npatch = max(1, (1 << 26) // e ** 3)
+        bt = wombat.Batch([(e, e, e)] * npatch, 1.0 / e, precision=wombat.WW_FP32_MIXED)
+        ar = bt.new_arena()
+        u = inputs.turbulence((e, e, e), mach=1.0, beta=100.0, seed=4000, dx=1.0 / e, device="cuda").float()
+        for p in range(npatch):
+            bt.view(ar, p).copy_(u)
+        torch.cuda.synchronize()
+        cache = os.path.join(tempfile.mkdtemp(), "sweep_tune.jsonl")
+        bt.autotune(ar, cache)
+        ft, bpc, nb = bt.shape()
+        bt.graph_steps(ar, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.graph_steps(ar, a.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        zones = npatch * e ** 3
+        rows.append({"edge": e, "patches": npatch, "zones": zones, "value": zones * 4 * a.steps / el,
+                     "ms_per_step": el / a.steps * 1e3, "faces_per_tile": ft, "blocks_per_cu": bpc})
+        print(f"[bench] patch sweep {e}^3 x {npatch}: {rows[-1]['value']:.3e} zone-stage/s",
+              file=sys.stderr, flush=True)
+        del bt, ar
+        torch.cuda.empty_cache()
+    return rows
 
 
 def shocked_turbulence(n, seed, wombat, inputs, pre, snaps=()):
@@ -318,6 +355,10 @@ def main():
     from paper_1808_10633_amd import inputs, opcount, wombat
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.patch_sweep:
+        print(json.dumps({"patch_sweep": patch_sweep(a, wombat, inputs), "unit": "zone-stage updates/s",
+                          "dtype": "f32 (f64 islands)", "steps": a.steps}), flush=True)
+        return
     n = a.n
     u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")
     u_ic = u.clone()
