@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-router form")
     ap.add_argument("--patch-sweep", action="store_true",
                     help="only run the batched form at uniform patch sizes 8^3..64^3 (one JSON line)")
+    ap.add_argument("--weights-ablation", action="store_true",
+                    help="WENO-JS vs WENO-Z: cost at --n and robustness on shocked turbulence (own JSON line)")
+    ap.add_argument("--abl-steps", type=int, default=300)
     ap.add_argument("--learned-n", type=int, default=512)
     ap.add_argument("--train-n", type=int, default=256)
     ap.add_argument("--pre-steps", type=int, default=200,
@@ -325,6 +328,66 @@ def learned_form(a, wombat, inputs, router):
     return res
 
 
+def weights_ablation(a, wombat, inputs):
+    """WENO-JS (eq. (3), the paper's weights) against WENO-Z (Borges et al.
+    2008, exponent 1) on the single-grid operator.  Cost: event-timed sweeps
+    and timed steps at n^3 on the rms-Mach-1 turbulence of the default line,
+    both precisions.  Robustness: the shocked turbulence recipe (beta 10,
+    10 % compressive, log-normal density sigma 0.5) at rms Mach 3, 6 and 10
+    on 64^3..256^3, each run up to `abl_steps` CFL-0.4 steps; a run fails at
+    the step whose CFL reduction finds rho <= 0, p <= 0 or a non-finite value."""
+    import torch
+    n = a.n
+    cost = {}
+    for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
+        P = wombat.WW_FP64 if prec == "fp64" else wombat.WW_FP32_MIXED
+        for wname, w in (("js", wombat.WEIGHTS_JS), ("z", wombat.WEIGHTS_Z)):
+            u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda").to(dt_).contiguous()
+            ctx = wombat.Context(n, n, n, precision=P, cfl=0.4, weights=w)
+            for _ in range(a.warmup):
+                ctx.step(u, 0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                ctx.step(u, 0.0)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ms = ctx.time_kernels(u, reps=a.reps)
+            cost[f"{prec}_{wname}"] = {"value": n ** 3 * 4 * a.steps / el, "ms_per_step": el / a.steps * 1e3,
+                                       "sweep_ms_xyz": ms[1:4], "update_ms": ms[4]}
+            print(f"[bench] ablation cost {prec} {wname}: {cost[f'{prec}_{wname}']['value']:.3e} "
+                  f"zone-stage/s, sweeps {sum(ms[1:4]):.2f} ms", file=sys.stderr, flush=True)
+            del ctx, u
+            torch.cuda.empty_cache()
+    runs = []
+    for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
+        P = wombat.WW_FP64 if prec == "fp64" else wombat.WW_FP32_MIXED
+        for m in (3.0, 6.0, 10.0):
+            for e in (64, 128, 256):
+                row = {"precision": prec, "mach": m, "n": e}
+                for wname, w in (("js", wombat.WEIGHTS_JS), ("z", wombat.WEIGHTS_Z)):
+                    u = inputs.turbulence((e, e, e), mach=m, beta=10.0, seed=6000, compressive_fraction=0.1,
+                                          lognormal_sigma=0.5, device="cuda").to(dt_).contiguous()
+                    ctx = wombat.Context(e, e, e, precision=P, cfl=0.4, weights=w)
+                    t, fail = 0.0, None
+                    for s in range(1, a.abl_steps + 1):
+                        try:
+                            t += ctx.step(u, 0.0)
+                        except wombat.WenoError as err:
+                            if err.code != -5:
+                                raise
+                            fail = s
+                            break
+                    row[wname] = {"failed_at_step": fail, "t_reached": t}
+                    del ctx, u
+                print(f"[bench] ablation {prec} Mach {m:g} {e}^3: JS {row['js']} Z {row['z']}",
+                      file=sys.stderr, flush=True)
+                runs.append(row)
+                torch.cuda.empty_cache()
+    return {"cost": cost, "cost_workload": f"rms Mach 1 beta 100 turbulence {n}^3, {a.steps} steps",
+            "robustness": runs, "max_steps": a.abl_steps}
+
+
 def cpu_baseline(n):
     """Serial FP64 oracle: one full RK4 step of the same turbulence recipe on
     an n^3 box (a bounded sample of the 512^3 workload)."""
@@ -358,6 +421,10 @@ def main():
     if a.patch_sweep:
         print(json.dumps({"patch_sweep": patch_sweep(a, wombat, inputs), "unit": "zone-stage updates/s",
                           "dtype": "f32 (f64 islands)", "steps": a.steps}), flush=True)
+        return
+    if a.weights_ablation:
+        print(json.dumps({"weights_ablation": weights_ablation(a, wombat, inputs),
+                          "unit": "zone-stage updates/s"}), flush=True)
         return
     n = a.n
     u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")

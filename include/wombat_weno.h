@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define WOMBAT_WENO_ABI_VERSION 1
+#define WOMBAT_WENO_ABI_VERSION 2
 
 typedef enum {
     WW_OK = 0,
@@ -70,6 +70,13 @@ typedef enum {
 } ww_status;
 
 typedef enum { WW_FP64 = 0, WW_FP32_MIXED = 1 } ww_precision;
+/* Nonlinear weights of the interpolant.  WW_WEIGHTS_JS: eq. (3)-(5), the
+ * paper's choice (Sec. 2.1).  WW_WEIGHTS_Z: the WENO-Z weights of Borges et
+ * al. (2008) with exponent 1, alpha_k = d_k (1 + tau5 / (eps + IS_k)),
+ * tau5 = |IS_0 - IS_2|, same smoothness indicators, linear weights and eps;
+ * offered for the comparison the paper argues (JS is the more robust of the
+ * two at shocks), on the single-grid operator only. */
+typedef enum { WW_WEIGHTS_JS = 0, WW_WEIGHTS_Z = 1 } ww_weights;
 typedef enum { WW_BC_PERIODIC = 0, WW_BC_OUTFLOW = 1, WW_BC_USER = 2 } ww_bc;
 
 /* User boundary hook: called for each WW_BC_USER face (0..5 = -x,+x,-y,+y,
@@ -94,6 +101,8 @@ typedef struct {
     void *user_bc_ctx;       /* passed back to user_bc                         */
     void *stream;            /* hipStream_t for all work; NULL = null stream   */
     int device;              /* HIP device ordinal                             */
+    int weights;             /* ww_weights (added in ABI 2); the batched and
+                                learned forms accept WW_WEIGHTS_JS only        */
 } wombat_weno_config;
 
 typedef struct wombat_weno wombat_weno_t;
@@ -102,7 +111,8 @@ typedef struct wombat_weno wombat_weno_t;
 int wombat_weno_abi_version(void);
 
 /* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
- * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0.
+ * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0,
+ * WW_WEIGHTS_JS.
  * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
 int wombat_weno_config_default(wombat_weno_config *cfg);
 

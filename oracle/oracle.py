@@ -39,7 +39,7 @@ class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("eps", C.c_double),
-                ("bc", C.c_int * 6)]
+                ("bc", C.c_int * 6), ("weights", C.c_int)]
 
 
 @dataclass
@@ -55,12 +55,14 @@ class Grid:
     cfl: float = 0.4
     eps: float = 1e-6
     bc: tuple = field(default_factory=lambda: (0, 0, 0, 0, 0, 0))   # 0 periodic, 1 outflow
+    weights: int = 0          # 0: weights of eq. (3); 1: WENO-Z (ablation)
 
     def c(self) -> _Grid:
         g = _Grid(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
                   self.gamma, self.cfl, self.eps)
         for i in range(6):
             g.bc[i] = int(self.bc[i])
+        g.weights = int(self.weights)
         return g
 
     @property
@@ -89,9 +91,13 @@ def lib():
         d = C.c_double
         L.orc_weno_weights.argtypes = [d, d, d, d, d, _dp, _dp]
         L.orc_weno_phi.argtypes = [d, d, d, d, d]
+        L.orc_weno_weights_z.argtypes = [d, d, d, d, d, _dp, _dp]
+        L.orc_interface_flux_z.argtypes = [_dp, d, d, _dp]
         L.orc_weno_phi.restype = d
         L.orc_weno_field_flux.argtypes = [_dp, _dp, d, d]
         L.orc_weno_field_flux.restype = d
+        L.orc_weno_field_flux_z.argtypes = [_dp, _dp, d, d]
+        L.orc_weno_field_flux_z.restype = d
         L.orc_prim_to_cons.argtypes = [_dp, d, _dp]
         L.orc_cons_to_prim.argtypes = [_dp, d, _dp]
         L.orc_flux.argtypes = [_dp, C.c_int, d, _dp]
@@ -132,12 +138,25 @@ def weno_weights(a, b, c, d, eps=1e-6):
     return w, s
 
 
+def weno_weights_z(a, b, c, d, eps=1e-6):
+    """WENO-Z weights (Borges et al. 2008, exponent 1): an ablation."""
+    w = np.zeros(3)
+    s = np.zeros(3)
+    lib().orc_weno_weights_z(a, b, c, d, eps, w, s)
+    return w, s
+
+
 def weno_phi(a, b, c, d, eps=1e-6):
     return lib().orc_weno_phi(a, b, c, d, eps)
 
 
 def weno_field_flux(f, u, alpha, eps=1e-6):
     return lib().orc_weno_field_flux(_f64(f), _f64(u), float(alpha), eps)
+
+
+def weno_field_flux_z(f, u, alpha, eps=1e-6):
+    """eq. (1) for one field with the WENO-Z weights (ablation)."""
+    return lib().orc_weno_field_flux_z(_f64(f), _f64(u), float(alpha), eps)
 
 
 # ---- point functions ----
@@ -177,6 +196,13 @@ def eigensystem(Wn, gamma=5.0 / 3.0):
 def interface_flux(Us, gamma=5.0 / 3.0, eps=1e-6):
     F = np.zeros(8)
     lib().orc_interface_flux(_f64(np.asarray(Us).reshape(48)), gamma, eps, F)
+    return F
+
+
+def interface_flux_z(Us, gamma=5.0 / 3.0, eps=1e-6):
+    """The characteristic flux with the WENO-Z weights (ablation)."""
+    F = np.zeros(8)
+    lib().orc_interface_flux_z(_f64(np.asarray(Us, dtype=np.float64).reshape(-1)), gamma, eps, F)
     return F
 
 

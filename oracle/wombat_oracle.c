@@ -71,19 +71,62 @@ void orc_weno_weights(double a, double b, double c, double d, double eps,
     if (is) { is[0] = is0; is[1] = is1; is[2] = is2; }
 }
 
+/* WENO-Z weights (Borges, Carmona, Costa & Don 2008; an ablation, not the
+ * paper's scheme, which keeps the weights of eq. 3 and argues in Sec. 2.1
+ * that they are the more robust choice): with the same IS_k and
+ * tau5 = |IS_0 - IS_2|, alpha_k = d_k (1 + tau5 / (eps + IS_k)), exponent 1. */
+void orc_weno_weights_z(double a, double b, double c, double d, double eps,
+                        double omega[3], double is[3])
+{
+    double is0 = 13.0 * (a - b) * (a - b) + 3.0 * (a - 3.0 * b) * (a - 3.0 * b);
+    double is1 = 13.0 * (b - c) * (b - c) + 3.0 * (b + c) * (b + c);
+    double is2 = 13.0 * (c - d) * (c - d) + 3.0 * (3.0 * c - d) * (3.0 * c - d);
+    double tau = fabs(is0 - is2);
+    double al0 = 1.0 * (1.0 + tau / (eps + is0));
+    double al1 = 6.0 * (1.0 + tau / (eps + is1));
+    double al2 = 3.0 * (1.0 + tau / (eps + is2));
+    double sum = al0 + al1 + al2;
+    omega[0] = al0 / sum;
+    omega[1] = al1 / sum;
+    omega[2] = al2 / sum;
+    if (is) { is[0] = is0; is[1] = is1; is[2] = is2; }
+}
+
+static double phi_mode(int z, double a, double b, double c, double d, double eps)
+{
+    double w[3];
+    if (z) orc_weno_weights_z(a, b, c, d, eps, w, NULL);
+    else orc_weno_weights(a, b, c, d, eps, w, NULL);
+    return w[0] * (a - 2.0 * b + c) / 3.0 + (w[2] - 0.5) * (b - 2.0 * c + d) / 6.0;
+}
+
 /* The WENO5 interpolant phi_N(a,b,c,d), eq. (2). */
 double orc_weno_phi(double a, double b, double c, double d, double eps)
 {
-    double w[3];
-    orc_weno_weights(a, b, c, d, eps, w, NULL);
-    return w[0] * (a - 2.0 * b + c) / 3.0 + (w[2] - 0.5) * (b - 2.0 * c + d) / 6.0;
+    return phi_mode(0, a, b, c, d, eps);
 }
+
+static double field_flux_mode(int z, const double f[6], const double u[6], double alpha,
+                              double eps);
 
 /* Interface flux of one decoupled field, eq. (1).
  * f[0..5], u[0..5]: the field's projected flux and state at cells i-2..i+3;
  * the interface is i+1/2.  Lax-Friedrichs splitting with speed alpha. */
 double orc_weno_field_flux(const double f[6], const double u[6], double alpha,
                            double eps)
+{
+    return field_flux_mode(0, f, u, alpha, eps);
+}
+
+/* The same with the WENO-Z weights (ablation). */
+double orc_weno_field_flux_z(const double f[6], const double u[6], double alpha,
+                             double eps)
+{
+    return field_flux_mode(1, f, u, alpha, eps);
+}
+
+static double field_flux_mode(int z, const double f[6], const double u[6], double alpha,
+                              double eps)
 {
     double fp[6], fm[6], dp[5], dm[5];
     int j;
@@ -98,8 +141,8 @@ double orc_weno_field_flux(const double f[6], const double u[6], double alpha,
     }
     double central = (-f[1] + 7.0 * f[2] + 7.0 * f[3] - f[4]) / 12.0;
     return central
-         - orc_weno_phi(dp[0], dp[1], dp[2], dp[3], eps)
-         + orc_weno_phi(dm[4], dm[3], dm[2], dm[1], eps);
+         - phi_mode(z, dp[0], dp[1], dp[2], dp[3], eps)
+         + phi_mode(z, dm[4], dm[3], dm[2], dm[1], eps);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -352,8 +395,23 @@ static double weight_deviation(const double f[6], const double u[6], double alph
  * max(|v_n| + c_f) over the stencil for every field.  *dev (may be NULL)
  * receives the largest deviation of any weight of any field from the linear
  * weights -- the label of a troubled interface. */
+static void interface_flux_mode(int z, const double Us[48], double gamma, double eps,
+                                int common_alpha, double Fhat[8], double *dev);
+
 void orc_interface_flux_ex(const double Us[48], double gamma, double eps,
                            int common_alpha, double Fhat[8], double *dev)
+{
+    interface_flux_mode(0, Us, gamma, eps, common_alpha, Fhat, dev);
+}
+
+/* The characteristic flux with the WENO-Z weights (ablation). */
+void orc_interface_flux_z(const double Us[48], double gamma, double eps, double Fhat[8])
+{
+    interface_flux_mode(1, Us, gamma, eps, 0, Fhat, NULL);
+}
+
+static void interface_flux_mode(int z, const double Us[48], double gamma, double eps,
+                                int common_alpha, double Fhat[8], double *dev)
 {
     double F[6][8], lamc[6][8], W[6][8], Wm[8], lam[8], L[64], R[64], Fs[8];
     int j, c, s;
@@ -389,7 +447,7 @@ void orc_interface_flux_ex(const double Us[48], double gamma, double eps,
             if (fabs(lamc[j][s]) > alpha) alpha = fabs(lamc[j][s]);
         }
         if (common_alpha && s < 7) alpha = acommon;   /* the B_n identity row keeps 0 */
-        Fs[s] = orc_weno_field_flux(fs, us, alpha, eps);
+        Fs[s] = field_flux_mode(z, fs, us, alpha, eps);
         if (dev && s < 7) {
             double dv = weight_deviation(fs, us, alpha, eps);
             if (dv > dmax) dmax = dv;
@@ -613,6 +671,7 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
                 if (nonphysical(Us + 8 * j, gr->gamma)) bad = 1;
             }
             if (linear) orc_linear_flux(Us, gr->gamma, Fh);
+            else if (gr->weights) orc_interface_flux_z(Us, gr->gamma, gr->eps, Fh);
             else orc_interface_flux(Us, gr->gamma, gr->eps, Fh);
             long fi = fidx(&FF[d], pos[0], pos[1], pos[2]);
             for (c = 0; c < 8; ++c) FF[d].f[perm[c] * FF[d].total + fi] = Fh[c];

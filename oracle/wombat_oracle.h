@@ -34,14 +34,22 @@ typedef struct {
     double cfl;            /* Courant number for orc_cfl_dt                    */
     double eps;            /* WENO epsilon (the paper's value is 1e-6)         */
     int bc[6];             /* faces -x,+x,-y,+y,-z,+z: 0 periodic, 1 outflow   */
+    int weights;           /* 0: weights of eq. (3); 1: WENO-Z (ablation)      */
 } orc_grid;
 
 /* ---- scalar WENO5 pieces (Sec. 2.1, eqs. 1-7) ---- */
 void   orc_weno_weights(double a, double b, double c, double d, double eps,
                         double omega[3], double is[3]);
 double orc_weno_phi(double a, double b, double c, double d, double eps);
+/* WENO-Z weights (Borges et al. 2008, exponent 1): an ablation. */
+void   orc_weno_weights_z(double a, double b, double c, double d, double eps,
+                          double omega[3], double is[3]);
+void   orc_interface_flux_z(const double Us[48], double gamma, double eps, double Fhat[8]);
 double orc_weno_field_flux(const double f[6], const double u[6],
                            double alpha, double eps);
+/* eq. (1) for one field with the WENO-Z weights (ablation). */
+double orc_weno_field_flux_z(const double f[6], const double u[6],
+                             double alpha, double eps);
 
 /* ---- ideal-MHD point functions (grid frame, 8 conserved variables) ---- */
 void orc_prim_to_cons(const double W[8], double gamma, double U[8]);

@@ -105,6 +105,7 @@ int validate(const wombat_weno_config *c, std::string &why)
     if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) { why = "cfl must be in (0, 1]"; return WW_ERR_INVALID_ARG; }
     if (!(c->eps > 0.0) || !std::isfinite(c->eps)) { why = "eps must be finite and > 0"; return WW_ERR_INVALID_ARG; }
     if (c->precision != WW_FP64 && c->precision != WW_FP32_MIXED) { why = "unknown precision"; return WW_ERR_INVALID_ARG; }
+    if (c->weights != WW_WEIGHTS_JS && c->weights != WW_WEIGHTS_Z) { why = "unknown weights"; return WW_ERR_INVALID_ARG; }
     bool user = false;
     for (int f = 0; f < 6; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
@@ -244,7 +245,7 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
                 continue;
             }
         }
-        WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->st));
+        WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
     }
     WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, (const T *)c->ff[0],
                                      (const T *)c->ff[1], (const T *)c->ff[2], c->F, c->G, k,
@@ -278,7 +279,7 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
                     WW_CHECK(c, ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
             } else if (which <= 3) {
                 int d = which - 1;
-                WW_CHECK(c, ww::launch_sweep<T>(d, u, (T *)c->ff[d], c->G, c->F[d], P, c->st));
+                WW_CHECK(c, ww::launch_sweep<T>(d, u, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
             } else {
                 WW_CHECK(c, ww::launch_update<T>(nullptr, nullptr, nullptr, (T *)c->work[0],
                                                  (const T *)c->ff[0], (const T *)c->ff[1],
@@ -609,6 +610,8 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
     if (rc) return rc;
     if (ctx->cfg.precision != WW_FP32_MIXED)
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs on FP32 contexts");
+    if (ctx->cfg.weights != WW_WEIGHTS_JS)
+        return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router routes to the WENO-JS flux only");
     if (!d_theta) { ctx->router = 0; return WW_OK; }
     if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
     if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");

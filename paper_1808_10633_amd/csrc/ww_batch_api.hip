@@ -270,6 +270,8 @@ int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int3
         return bfail(nullptr, WW_ERR_INVALID_ARG, "need gamma > 1, cfl in (0,1], eps > 0");
     if (cfg->precision != WW_FP64 && cfg->precision != WW_FP32_MIXED)
         return bfail(nullptr, WW_ERR_INVALID_ARG, "unknown precision");
+    if (cfg->weights != WW_WEIGHTS_JS)
+        return bfail(nullptr, WW_ERR_UNSUPPORTED, "the batched form uses the WENO-JS weights only");
     for (int p = 0; p < npatch; ++p)
         for (int d = 0; d < 3; ++d)
             if (dims[3 * p + d] < 8 || dims[3 * p + d] > 1024)

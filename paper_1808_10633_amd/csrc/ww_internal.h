@@ -37,9 +37,11 @@ struct Phys {
 };
 
 // Launchers (return the hipError_t of the launch).
+// weights: WEIGHTS_JS (eq. (3)-(5)) or WEIGHTS_Z (Borges et al. 2008).
+constexpr int WEIGHTS_JS = 0, WEIGHTS_Z = 1;
 template <typename T>
 hipError_t launch_sweep(int dir, const T *u, T *flux, const Geom &G, const FaceBox &F,
-                        const Phys &P, hipStream_t st);
+                        const Phys &P, int weights, hipStream_t st);
 
 // mode 0: out = L(U); mode 1: RK stage (stage s, coefficients below).
 struct StageCoef {

@@ -61,7 +61,9 @@ __device__ __forceinline__ float frcp(float x)
 }
 
 // phi_N of eq. (2) with the weights of eqs. (3)-(7).  e4 = epsilon / 4.
-template <typename T, bool LBL = false>
+// WZ: the WENO-Z weights of Borges et al. (2008) instead (exponent 1, an
+// ablation): alpha_k = d_k (1 + tau5 / (eps + IS_k)), tau5 = |IS_0 - IS_2|.
+template <typename T, bool LBL = false, bool WZ = false>
 __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
 {
     // Smoothness indicators of eqs. (5)-(7), expanded into the quadratic forms
@@ -80,10 +82,20 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
         const T s = frcp(fmax(q0, fmax(q1, q2)));
         q0 *= s; q1 *= s; q2 *= s;
     }
-    q0 *= q0; q1 *= q1; q2 *= q2;
-    // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
-    // written over the common denominator q0 q1 q2 (one reciprocal).
-    T n0 = q1 * q2, n1 = T(6) * q0 * q2, n2 = T(3) * q0 * q1;
+    T n0, n1, n2;
+    if constexpr (WZ) {
+        // alpha_k = d_k (q_k + t) / q_k with t = |q_0 - q_2| (= tau5 / 4),
+        // over the common denominator q0 q1 q2
+        const T t = fabs(q0 - q2);
+        n0 = (q0 + t) * q1 * q2;
+        n1 = T(6) * (q1 + t) * q0 * q2;
+        n2 = T(3) * (q2 + t) * q0 * q1;
+    } else {
+        q0 *= q0; q1 *= q1; q2 *= q2;
+        // alpha_k = d_k / q_k with d = (1, 6, 3); omega_k = alpha_k / sum alpha,
+        // written over the common denominator q0 q1 q2 (one reciprocal).
+        n0 = q1 * q2; n1 = T(6) * q0 * q2; n2 = T(3) * q0 * q1;
+    }
     T inv = frcp(n0 + n1 + n2);
     if constexpr (LBL) {
         // largest deviation of (omega_0, omega_1, omega_2) from (0.1, 0.6, 0.3)
@@ -100,7 +112,7 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
 // eq. (1) for one field.  cc: projected central term; df, du: projected flux
 // and state differences (k = 0..4 at i-3/2 .. i+5/2), both already carrying
 // the 1/2 of the Lax-Friedrichs split; al: LF speed.
-template <typename T, bool LBL = false>
+template <typename T, bool LBL = false, bool WZ = false>
 __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps,
                                         T *dev = nullptr)
 {
@@ -110,8 +122,8 @@ __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5]
         dp[k] = fma(al, du[k], df[k]);
         dm[k] = fma(-al, du[k], df[k]);
     }
-    return cc - phi_n<T, LBL>(dp[0], dp[1], dp[2], dp[3], eps, dev)
-              + phi_n<T, LBL>(dm[4], dm[3], dm[2], dm[1], eps, dev);
+    return cc - phi_n<T, LBL, WZ>(dp[0], dp[1], dp[2], dp[3], eps, dev)
+              + phi_n<T, LBL, WZ>(dm[4], dm[3], dm[2], dm[1], eps, dev);
 }
 
 // Stage one cell: sweep-frame conserved variables and derived quantities.
@@ -149,7 +161,7 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // out: sweep-frame flux (rho, mn, mt1, mt2, Bt1, Bt2, E).
 // LBL: also return in *dev the largest deviation of any weight of any field
 // from the linear weights (the label of a troubled interface).
-template <typename T, bool LBL = false>
+template <typename T, bool LBL = false, bool WZ = false>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
                                           double gamma, double igm1, T eps, T (&out)[7],
                                           T *dev = nullptr)
@@ -268,10 +280,10 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         T df[5], du[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] + odf[k]; du[k] = edu[k] + odu[k]; }
-        T fplus = weno_field<T, LBL>(ec + oc, df, du, am[hi], teps, dev);
+        T fplus = weno_field<T, LBL, WZ>(ec + oc, df, du, am[hi], teps, dev);
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] - odf[k]; du[k] = edu[k] - odu[k]; }
-        T fminus = weno_field<T, LBL>(ec - oc, df, du, am[lo], teps, dev);
+        T fminus = weno_field<T, LBL, WZ>(ec - oc, df, du, am[lo], teps, dev);
         S = fplus + fminus;
         D = fplus - fminus;
     };
@@ -305,7 +317,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
             df[k] = kh * (dY[k][0] - ke6 * dY[k][6]);
             du[k] = kh * (dZ[k][0] - ke6 * dZ[k][6]);
         }
-        G[0] += weno_field<T, LBL>(cc, df, du, am[3], teps, dev);
+        G[0] += weno_field<T, LBL, WZ>(cc, df, du, am[3], teps, dev);
     }
 
     // back to (vt1, vt2), (Bt1, Bt2) and through dU/dW
@@ -388,7 +400,7 @@ __device__ __forceinline__ void store_face(T *__restrict__ flux, const FaceBox &
 template <int DIR, int FT>
 __host__ __device__ constexpr int tile_cells() { return DIR == 0 ? ROWS * NCX : TILE * (FT + 5); }
 
-template <int DIR, int FT, typename T>
+template <int DIR, int FT, typename T, bool WZ = false>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restrict__ flux,
                                            const Geom &G, const FaceBox &F, const Phys &P,
                                            int ta, int tb, T *sq)
@@ -421,7 +433,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
         pos[2] = F.lo[2] + row / F.cnt[1];
         if (row < nrows && pos[0] < F.cnt[0]) {
             T out[7];
-            face_flux<T>(sq, NC, w * NCX + lane, 1, P.gamma, P.igm1, (T)P.eps, out);
+            face_flux<T, false, WZ>(sq, NC, w * NCX + lane, 1, P.gamma, P.igm1, (T)P.eps, out);
             store_face<N, T>(flux, F, pos, out);
         }
     } else {
@@ -446,7 +458,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
             pos[N] = f0 + ff;
             if (p < npos && pos[N] < F.cnt[N]) {
                 T out[7];
-                face_flux<T>(sq, NC, ff * TILE + lane, TILE, P.gamma, P.igm1, (T)P.eps, out);
+                face_flux<T, false, WZ>(sq, NC, ff * TILE + lane, TILE, P.gamma, P.igm1, (T)P.eps, out);
                 store_face<N, T>(flux, F, pos, out);
             }
         }
@@ -589,7 +601,7 @@ __device__ __forceinline__ bool xseg_face(const FaceBox &F, const XSeg &X, int t
     return tid < X.nface;
 }
 
-template <typename T>
+template <typename T, bool WZ = false>
 __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__restrict__ flux,
                                                 const Geom &G, const FaceBox &F, const Phys &P,
                                                 long tile, T *sq)
@@ -600,7 +612,7 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
     int pos[3], off;
     if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T, false, WZ>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out);
         store_face<0, T>(flux, F, pos, out);
     }
 }
@@ -650,7 +662,7 @@ __device__ __forceinline__ bool yz_face(const FaceBox &F, int ta, int tb, int ti
     return p < npos && pos[N] < F.cnt[N];
 }
 
-template <int DIR, int PW, typename T>
+template <int DIR, int PW, typename T, bool WZ = false>
 __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__restrict__ flux,
                                               const Geom &G, const FaceBox &F, const Phys &P,
                                               int ta, int tb, T *sq)
@@ -660,7 +672,7 @@ __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__rest
     int pos[3], off;
     if (yz_face<DIR, PW>(F, ta, tb, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T>(sq, yz_cells<PW>(), off, PW, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T, false, WZ>(sq, yz_cells<PW>(), off, PW, P.gamma, P.igm1, (T)P.eps, out);
         store_face<DIR, T>(flux, F, pos, out);
     }
 }

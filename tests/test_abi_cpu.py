@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wombat_weno_abi_version() == 1
+    assert lib.wombat_weno_abi_version() == 2 == wombat.ABI_VERSION
 
 
 def _cfg(**kw):
@@ -74,6 +74,8 @@ def test_default_config_is_valid(lib):
     (dict(dx=-1.0), "widths"),
     (dict(dz=float("nan")), "widths"),
     (dict(precision=7), "precision"),
+    (dict(weights=2), "weights"),
+    (dict(weights=-1), "weights"),
     (dict(bc=(0, 1, 0, 0, 0, 0)), "both faces"),
     (dict(bc=(2, 2, 0, 0, 0, 0)), "user_bc"),
     (dict(bc=(5, 5, 0, 0, 0, 0)), "unknown boundary"),
@@ -104,3 +106,16 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(wombat, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         wombat.lib()
+
+
+def test_weights_default_and_batched_rejects_z(lib):
+    cfg = _cfg()
+    assert cfg.weights == wombat.WEIGHTS_JS
+    cfg.weights = wombat.WEIGHTS_Z
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == 0
+    # the batched form is JS-only: refused before any device work
+    dims = (C.c_int32 * 3)(16, 16, 16)
+    h = C.c_void_p(1234)
+    assert lib.wombat_weno_batch_init(C.byref(cfg), 1, dims, C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
+    assert "WENO-JS" in lib.wombat_weno_batch_last_error(None).decode()
+    assert h.value == 1234

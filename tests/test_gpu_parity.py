@@ -114,6 +114,74 @@ def test_rhs_parity(case):
     assert err < TOL
 
 
+# WENO-Z weights (the ablation): every sweep tile kind -- x rows under 86
+# faces, flattened x segments, the y and z tiles -- smooth and shocked data.
+WENOZ_CASES = ["turb_67x10x9", "turb_100x7x6", "smooth_13x70x11", "smooth_9x8x71", "brio_wu_1d",
+               "xz_2d_outflow"]
+
+
+@pytest.mark.parametrize("case", WENOZ_CASES)
+def test_rhs_parity_wenoz(case):
+    say(f"[rhs parity, WENO-Z] {case}")
+    g, u = rhs_case(case)
+    g.weights = 1
+    ref = O.rhs(g, u)
+    g.weights = 0
+    ref_js = O.rhs(g, u)
+    ctx = ctx_for(g, weights=W.WEIGHTS_Z)
+    ug = to_gpu(u)
+    dg = torch.zeros_like(ug)
+    ctx.rhs(ug, dg)
+    torch.cuda.synchronize()
+    dxmin = min(d for d, n in ((g.dx, g.nx), (g.dy, g.ny), (g.dz, g.nz)) if n > 1)
+    err, per = scaled_rhs_error(g.interior(dg.cpu().numpy()), g.interior(ref), g.interior(u), dxmin)
+    gap, _ = scaled_rhs_error(g.interior(ref_js), g.interior(ref), g.interior(u), dxmin)
+    say(f"  max scaled error {err:.3e} (JS vs Z in the oracle: {gap:.3e})")
+    assert err < TOL
+    assert gap > 1e3 * TOL       # the case does tell the two weight families apart
+
+
+def test_wenoz_brio_wu_10_steps():
+    say("[WENO-Z] Brio-Wu 200 cells, 10 steps")
+    g, u = rhs_case("brio_wu_1d")
+    g.weights = 1
+    ctx = ctx_for(g, weights=W.WEIGHTS_Z)
+    ug = to_gpu(u)
+    ref = u.copy()
+    for step in range(10):
+        dtg = ctx.cfl_dt(ug)
+        dto = O.cfl_dt(g, ref)
+        assert abs(dtg - dto) <= 1e-14 * dto
+        ctx.step(ug, dtg)
+        O.rk4_step(g, ref, dto)
+    err, _ = scaled_state_error(g.interior(ug.cpu().numpy()), g.interior(ref))
+    say(f"  scaled state error after 10 steps {err:.3e}")
+    assert err < TOL
+
+
+def test_wenoz_fp32_rhs_against_oracle():
+    n = 24
+    say("[WENO-Z fp32 rhs] 24^3 turbulence vs oracle")
+    g = O.Grid(n, n, n, 1 / n, 1 / n, 1 / n, weights=1)
+    u = I.turbulence((n, n, n), mach=1.0, beta=100.0, seed=77, kmax=8).numpy().copy()
+    ref = O.rhs(g, u)
+    ctx = W.Context(n, n, n, precision=W.WW_FP32_MIXED, weights=W.WEIGHTS_Z)
+    ug = torch.from_numpy(u).cuda().float()
+    dg = torch.zeros_like(ug)
+    ctx.rhs(ug, dg)
+    torch.cuda.synchronize()
+    err, _ = scaled_rhs_error(g.interior(dg.double().cpu().numpy()), g.interior(ref), g.interior(u), 1 / n)
+    say(f"  fp32 rhs scaled error {err:.3e}")
+    assert err < 2e-6
+
+
+def test_wenoz_refused_by_batched_and_learned_forms():
+    ctx = W.Context(16, 16, 16, precision=W.WW_FP32_MIXED, weights=W.WEIGHTS_Z)
+    theta = torch.zeros(W.mlp_param_count(), dtype=torch.float32, device="cuda")
+    with pytest.raises(W.WenoError, match="WENO-JS"):
+        ctx.set_router(theta, 0.5)
+
+
 def test_alfven_wave_32cube_10_steps_every_step():
     """The spec case: inclined Alfven wave, 32^3, CFL 0.4, 10 steps."""
     n = 32
