@@ -46,7 +46,7 @@
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, BX = 4, BY = 5, BZ = 6, EN = 7 };
 
 /* Degeneracy conventions for the eigenvectors (the paper is silent). */
-#define ORC_BT_TINY  1e-24   /* |B_t|^2/rho below this * (a^2 + b_n^2): beta = (1,1)/sqrt2 */
+#define ORC_BT_TINY  1e-24   /* |B_t|^2/rho below this * (a^2 + b_n^2): beta = (1,0) */
 #define ORC_CFS_TINY 1e-12   /* c_f^2 - c_s^2 below this * (a^2 + b^2): alpha_f=1, alpha_s=0 */
 
 /* ------------------------------------------------------------------------ */
@@ -273,7 +273,11 @@ void orc_eigensystem(const double Wn[8], double gamma,
         double bt = sqrt(Bt1 * Bt1 + Bt2 * Bt2);
         b1 = Bt1 / bt; b2 = Bt2 / bt;
     } else {
-        b1 = b2 = 1.0 / sqrt(2.0);
+        /* any unit vector spans the degenerate pair; the first transverse
+         * axis keeps the two transverse momenta in separate characteristic
+         * fields, so a flow without a component or gradient along one
+         * transverse axis gains none there */
+        b1 = 1.0; b2 = 0.0;
     }
     double s = (Bn >= 0.0) ? 1.0 : -1.0;
 

@@ -233,7 +233,11 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         double ibt = frcp(sqrt(b1b * b1b + b2b * b2b));
         be1 = b1b * ibt; be2 = b2b * ibt;
     } else {
-        be1 = be2 = 0.70710678118654752440;
+        // B_t ~ 0: any unit vector spans the degenerate wave pairs; the first
+        // transverse axis keeps the two transverse momenta in separate
+        // characteristic fields, so a planar flow (no component or gradient
+        // along one transverse axis) stays planar
+        be1 = 1.0; be2 = 0.0;
     }
     double sg = (bnb >= 0.0) ? 1.0 : -1.0;
     double cfm = sqrt(cf2), csm = sqrt(cs2), am_ = sqrt(a2), sr = sqrt(rb);

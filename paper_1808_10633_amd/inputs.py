@@ -20,6 +20,9 @@ Workloads (the paper's own test problems are analytic, Sec. 3.1):
     vector potential (so its corner divergence vanishes), optional log-normal
     density.
   * ``sod``, ``brio_wu``: 1-D shock tubes.
+  * ``field_loop``, ``orszag_tang``, ``kelvin_helmholtz``: the 2-D problems of
+    Sec. 3.1 (field-loop advection, the Orszag-Tang vortex, a Kelvin-Helmholtz
+    instability with the printed parameters).
 """
 from __future__ import annotations
 
@@ -324,11 +327,66 @@ def field_loop(n, gamma=GAMMA, amp=1e-3, radius=0.3, v=(2.0, 1.0)):
     X, Y = np.meshgrid(xc, yc, indexing="xy")     # (ny+1, nx+1)
     r = np.sqrt(X ** 2 + Y ** 2)
     A = np.where(r < radius, amp * (radius - r), 0.0)
-    bx_face = (A[1:, :] - A[:-1, :]) / dy          # at (x corners, y centres): (ny, nx+1)
-    by_face = -(A[:, 1:] - A[:, :-1]) / dx         # at (x centres, y corners): (ny+1, nx)
-    bx = 0.5 * (bx_face[:, 1:] + bx_face[:, :-1])  # (ny, nx)
-    by = 0.5 * (by_face[1:, :] + by_face[:-1, :])
+    bx, by = _curl_from_corner_potential(A, dx, dy)
     rho = np.ones((ny, nx))
     z = np.zeros((ny, nx))
     U = conserved(rho, [z + v[0], z + v[1], z], [bx, by, z], np.ones((ny, nx)), gamma)
+    return _pad(U[:, None, :, :], nx, ny, 1)
+
+
+def _curl_from_corner_potential(A, dx, dy):
+    """Cell-centred (Bx, By) of the field whose potential A_z is sampled at
+    the (ny+1, nx+1) cell corners: face fields are the discrete curl and the
+    cell field is the mean of its two faces, so the corner divergence of the
+    cell field vanishes."""
+    bx_face = (A[1:, :] - A[:-1, :]) / dy          # (ny, nx+1)
+    by_face = -(A[:, 1:] - A[:, :-1]) / dx         # (ny+1, nx)
+    return 0.5 * (bx_face[:, 1:] + bx_face[:, :-1]), 0.5 * (by_face[1:, :] + by_face[:-1, :])
+
+
+def orszag_tang(n, gamma=GAMMA):
+    """Orszag-Tang vortex (Sec. 3.1; the set-up of Stone et al. 2008 in
+    Heaviside-Lorentz units): periodic [-1/2, 1/2]^2 with n x n cells,
+    rho = 25/(36 pi), p = 5/(12 pi), v = (-sin 2 pi y, sin 2 pi x),
+    B = B0 (-sin 2 pi y, sin 4 pi x) with B0 = 1/sqrt(4 pi), from the potential
+    A_z = B0 (cos(4 pi x)/(4 pi) + cos(2 pi y)/(2 pi)) sampled at cell corners.
+    The state is symmetric under the point reflection (x, y) -> (-x, -y)
+    with v and B odd.  Returns a padded numpy array (8, 1, n + 6, n + 6)."""
+    d = 1.0 / n
+    xc = -0.5 + d * np.arange(n + 1)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    b0 = 1.0 / math.sqrt(4.0 * math.pi)
+    A = b0 * (np.cos(4 * math.pi * X) / (4 * math.pi) + np.cos(2 * math.pi * Y) / (2 * math.pi))
+    bx, by = _curl_from_corner_potential(A, d, d)
+    x = -0.5 + d * (np.arange(n) + 0.5)
+    Xc, Yc = np.meshgrid(x, x, indexing="xy")
+    rho = np.full((n, n), 25.0 / (36.0 * math.pi))
+    p = np.full((n, n), 5.0 / (12.0 * math.pi))
+    z = np.zeros((n, n))
+    U = conserved(rho, [-np.sin(2 * math.pi * Yc), np.sin(2 * math.pi * Xc), z], [bx, by, z], p, gamma)
+    return _pad(U[:, None, :, :], n, n, 1)
+
+
+def kelvin_helmholtz(nx, gamma=GAMMA, amp=0.01, p0=10.0, a=0.05, sigma=0.2, z1=0.5, z2=1.5,
+                     u_flow=1.0, drho=1.0):
+    """Kelvin-Helmholtz instability with the initial conditions of Lecoanet
+    et al. (2016) and the parameters Sec. 3.1 prints (A = 0.01, P = 10,
+    a = 0.05, sigma = 0.2, z1 = 0.5, z2 = 1.5, u_flow = 1, Delta rho = 1):
+    periodic box [0, 1] x [0, 2] with nx x 2nx cells (the second axis plays
+    z), B = 0,
+      u_x = u_flow (tanh((z - z1)/a) - tanh((z - z2)/a) - 1),
+      u_z = A sin(2 pi x) (exp(-(z - z1)^2/sigma^2) + exp(-(z - z2)^2/sigma^2)),
+      rho = 1 + (Delta rho / 2) (tanh((z - z1)/a) - tanh((z - z2)/a)),  p = P.
+    Returns a padded numpy array (8, 1, 2nx + 6, nx + 6)."""
+    ny = 2 * nx
+    d = 1.0 / nx
+    x = d * (np.arange(nx) + 0.5)
+    z = d * (np.arange(ny) + 0.5)
+    X, Z = np.meshgrid(x, z, indexing="xy")       # (ny, nx)
+    th = np.tanh((Z - z1) / a) - np.tanh((Z - z2) / a)
+    ux = u_flow * (th - 1.0)
+    uz = amp * np.sin(2 * math.pi * X) * (np.exp(-((Z - z1) / sigma) ** 2) + np.exp(-((Z - z2) / sigma) ** 2))
+    rho = 1.0 + 0.5 * drho * th
+    zero = np.zeros_like(X)
+    U = conserved(rho, [ux, uz, zero], [zero, zero, zero], np.full_like(X, p0), gamma)
     return _pad(U[:, None, :, :], nx, ny, 1)
