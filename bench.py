@@ -60,8 +60,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-router form")
     ap.add_argument("--patch-sweep", action="store_true",
                     help="only run the batched form at uniform patch sizes 8^3..64^3 (one JSON line)")
-    ap.add_argument("--weights-ablation", action="store_true",
-                    help="WENO-JS vs WENO-Z: cost at --n and robustness on shocked turbulence (own JSON line)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="scheme variants (WENO-Z weights, SSP-RK3): cost at --n and robustness on shocked "
+                         "turbulence (own JSON line)")
     ap.add_argument("--abl-steps", type=int, default=300)
     ap.add_argument("--learned-n", type=int, default=512)
     ap.add_argument("--train-n", type=int, default=256)
@@ -328,22 +329,28 @@ def learned_form(a, wombat, inputs, router):
     return res
 
 
-def weights_ablation(a, wombat, inputs):
-    """WENO-JS (eq. (3), the paper's weights) against WENO-Z (Borges et al.
-    2008, exponent 1) on the single-grid operator.  Cost: event-timed sweeps
-    and timed steps at n^3 on the rms-Mach-1 turbulence of the default line,
-    both precisions.  Robustness: the shocked turbulence recipe (beta 10,
-    10 % compressive, log-normal density sigma 0.5) at rms Mach 3, 6 and 10
-    on 64^3..256^3, each run up to `abl_steps` CFL-0.4 steps; a run fails at
-    the step whose CFL reduction finds rho <= 0, p <= 0 or a non-finite value."""
+ABLATIONS = (("rk4_js", "WEIGHTS_JS", "RK4"), ("rk4_z", "WEIGHTS_Z", "RK4"), ("ssprk3_js", "WEIGHTS_JS", "SSPRK3"))
+
+
+def ablation(a, wombat, inputs):
+    """Scheme variants on the single-grid operator: the paper's choice
+    (weights of eq. (3), classical RK4), WENO-Z weights (Borges et al. 2008,
+    exponent 1) and SSP-RK3 (Shu & Osher 1988).  Cost: timed steps and
+    event-timed kernels at n^3 on the rms-Mach-1 turbulence of the default
+    line, both precisions.  Robustness (FP64): the shocked turbulence recipe
+    (beta 10, 10 % compressive, log-normal density sigma 0.5, seed 6000) at
+    rms Mach 3, 6 and 10 on 64^3..256^3, each run up to `abl_steps` CFL-0.4
+    steps (every variant takes the same CFL time step rule); a run fails at the
+    step whose CFL reduction finds rho <= 0, p <= 0 or a non-finite value."""
     import torch
     n = a.n
     cost = {}
     for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
         P = wombat.WW_FP64 if prec == "fp64" else wombat.WW_FP32_MIXED
-        for wname, w in (("js", wombat.WEIGHTS_JS), ("z", wombat.WEIGHTS_Z)):
+        for name, wk, ik in ABLATIONS:
             u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda").to(dt_).contiguous()
-            ctx = wombat.Context(n, n, n, precision=P, cfl=0.4, weights=w)
+            ctx = wombat.Context(n, n, n, precision=P, cfl=0.4, weights=getattr(wombat, wk),
+                                 integrator=getattr(wombat, ik))
             for _ in range(a.warmup):
                 ctx.step(u, 0.0)
             torch.cuda.synchronize()
@@ -353,37 +360,41 @@ def weights_ablation(a, wombat, inputs):
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             ms = ctx.time_kernels(u, reps=a.reps)
-            cost[f"{prec}_{wname}"] = {"value": n ** 3 * 4 * a.steps / el, "ms_per_step": el / a.steps * 1e3,
-                                       "sweep_ms_xyz": ms[1:4], "update_ms": ms[4]}
-            print(f"[bench] ablation cost {prec} {wname}: {cost[f'{prec}_{wname}']['value']:.3e} "
-                  f"zone-stage/s, sweeps {sum(ms[1:4]):.2f} ms", file=sys.stderr, flush=True)
+            stages = 3 if ik == "SSPRK3" else 4
+            cost[f"{prec}_{name}"] = {"zone_steps_per_s": n ** 3 * a.steps / el,
+                                      "zone_stage_updates_per_s": n ** 3 * stages * a.steps / el,
+                                      "ms_per_step": el / a.steps * 1e3, "sweep_ms_xyz": ms[1:4],
+                                      "update_ms": ms[4]}
+            print(f"[bench] ablation cost {prec} {name}: {el / a.steps * 1e3:.1f} ms/step, "
+                  f"sweeps {sum(ms[1:4]):.2f} ms", file=sys.stderr, flush=True)
             del ctx, u
             torch.cuda.empty_cache()
     runs = []
-    for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
-        P = wombat.WW_FP64 if prec == "fp64" else wombat.WW_FP32_MIXED
-        for m in (3.0, 6.0, 10.0):
-            for e in (64, 128, 256):
-                row = {"precision": prec, "mach": m, "n": e}
-                for wname, w in (("js", wombat.WEIGHTS_JS), ("z", wombat.WEIGHTS_Z)):
-                    u = inputs.turbulence((e, e, e), mach=m, beta=10.0, seed=6000, compressive_fraction=0.1,
-                                          lognormal_sigma=0.5, device="cuda").to(dt_).contiguous()
-                    ctx = wombat.Context(e, e, e, precision=P, cfl=0.4, weights=w)
-                    t, fail = 0.0, None
-                    for s in range(1, a.abl_steps + 1):
-                        try:
-                            t += ctx.step(u, 0.0)
-                        except wombat.WenoError as err:
-                            if err.code != -5:
-                                raise
-                            fail = s
-                            break
-                    row[wname] = {"failed_at_step": fail, "t_reached": t}
-                    del ctx, u
-                print(f"[bench] ablation {prec} Mach {m:g} {e}^3: JS {row['js']} Z {row['z']}",
-                      file=sys.stderr, flush=True)
-                runs.append(row)
-                torch.cuda.empty_cache()
+    for m in (3.0, 6.0, 10.0):
+        for e in (64, 128, 256):
+            row = {"precision": "fp64", "mach": m, "n": e}
+            for name, wk, ik in ABLATIONS:
+                u = inputs.turbulence((e, e, e), mach=m, beta=10.0, seed=6000, compressive_fraction=0.1,
+                                      lognormal_sigma=0.5, device="cuda").contiguous()
+                ctx = wombat.Context(e, e, e, precision=wombat.WW_FP64, cfl=0.4, weights=getattr(wombat, wk),
+                                     integrator=getattr(wombat, ik))
+                t, s, fail = 0.0, 0, None
+                while s < a.abl_steps:
+                    s += 1
+                    try:
+                        t += ctx.step(u, 0.0)
+                    except wombat.WenoError as err:
+                        if err.code != -5:
+                            raise
+                        fail = s
+                        break
+                row[name] = {"failed_at_step": fail, "t_reached": t, "steps": s}
+                del ctx, u
+            print(f"[bench] ablation Mach {m:g} {e}^3: " +
+                  ", ".join(f"{k} {row[k]['failed_at_step']} (t {row[k]['t_reached']:.5f})" for k, _, _ in ABLATIONS),
+                  file=sys.stderr, flush=True)
+            runs.append(row)
+            torch.cuda.empty_cache()
     return {"cost": cost, "cost_workload": f"rms Mach 1 beta 100 turbulence {n}^3, {a.steps} steps",
             "robustness": runs, "max_steps": a.abl_steps}
 
@@ -422,9 +433,8 @@ def main():
         print(json.dumps({"patch_sweep": patch_sweep(a, wombat, inputs), "unit": "zone-stage updates/s",
                           "dtype": "f32 (f64 islands)", "steps": a.steps}), flush=True)
         return
-    if a.weights_ablation:
-        print(json.dumps({"weights_ablation": weights_ablation(a, wombat, inputs),
-                          "unit": "zone-stage updates/s"}), flush=True)
+    if a.ablation:
+        print(json.dumps({"ablation": ablation(a, wombat, inputs)}), flush=True)
         return
     n = a.n
     u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")

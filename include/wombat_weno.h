@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define WOMBAT_WENO_ABI_VERSION 2
+#define WOMBAT_WENO_ABI_VERSION 3
 
 typedef enum {
     WW_OK = 0,
@@ -77,6 +77,13 @@ typedef enum { WW_FP64 = 0, WW_FP32_MIXED = 1 } ww_precision;
  * offered for the comparison the paper argues (JS is the more robust of the
  * two at shocks), on the single-grid operator only. */
 typedef enum { WW_WEIGHTS_JS = 0, WW_WEIGHTS_Z = 1 } ww_weights;
+/* Time integrator of wombat_weno_step.  WW_RK4: the classical four-stage,
+ * fourth-order Runge-Kutta of Sec. 2.1 (low-storage form).  WW_SSPRK3: the
+ * three-stage, third-order strong-stability-preserving scheme of Shu &
+ * Osher (1988), u1 = u + dt L(u), u2 = 3/4 u + 1/4 (u1 + dt L(u1)),
+ * u^{n+1} = 1/3 u + 2/3 (u2 + dt L(u2)); an ablation of the paper's
+ * choice, single-grid operator and wombat_weno_step only. */
+typedef enum { WW_RK4 = 0, WW_SSPRK3 = 1 } ww_integrator;
 typedef enum { WW_BC_PERIODIC = 0, WW_BC_OUTFLOW = 1, WW_BC_USER = 2 } ww_bc;
 
 /* User boundary hook: called for each WW_BC_USER face (0..5 = -x,+x,-y,+y,
@@ -103,6 +110,9 @@ typedef struct {
     int device;              /* HIP device ordinal                             */
     int weights;             /* ww_weights (added in ABI 2); the batched and
                                 learned forms accept WW_WEIGHTS_JS only        */
+    int integrator;          /* ww_integrator (added in ABI 3); the batched
+                                and learned forms and wombat_weno_stage accept
+                                WW_RK4 only                                   */
 } wombat_weno_config;
 
 typedef struct wombat_weno wombat_weno_t;
@@ -112,7 +122,7 @@ int wombat_weno_abi_version(void);
 
 /* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
  * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0,
- * WW_WEIGHTS_JS.
+ * WW_WEIGHTS_JS, WW_RK4.
  * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
 int wombat_weno_config_default(wombat_weno_config *cfg);
 
@@ -167,11 +177,13 @@ int wombat_weno_rhs(wombat_weno_t *ctx, void *d_u, void *d_dudt);
  *   s=3:                          out = acc + dt/6 L(us)   (u0 unused)
  * Ghosts of d_us_in are filled first; interior cells of d_acc and d_us_out
  * are written.  d_us_out may alias d_u0 (pointwise), but not d_us_in or
- * d_acc.  dt must be finite and > 0.  Asynchronous. */
+ * d_acc.  dt must be finite and > 0.  Asynchronous.  WW_ERR_UNSUPPORTED on
+ * a context configured with WW_SSPRK3. */
 int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0,
                       void *d_us_in, void *d_acc, void *d_us_out);
 
-/* A full RK4 step of d_u in place using the context's work arrays.
+/* A full step of d_u in place using the context's work arrays: the four
+ * RK4 stages above, or the three SSP-RK3 stages with WW_SSPRK3.
  * dt <= 0 computes the CFL step first (synchronous; may return
  * WW_ERR_NONPHYSICAL).  *dt_used (may be NULL) receives the step taken.
  * Asynchronous when dt > 0. */

@@ -120,6 +120,8 @@ def lib():
         L.orc_cfl_dt.restype = d
         L.orc_rk4_step.argtypes = [g, _dp, d]
         L.orc_rk4_step.restype = C.c_int
+        L.orc_ssprk3_step.argtypes = [g, _dp, d]
+        L.orc_ssprk3_step.restype = C.c_int
         L.orc_sums.argtypes = [g, _dp, _dp]
         L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
         _lib = L
@@ -301,6 +303,15 @@ def rk4_step(grid: Grid, u, dt):
     rc = lib().orc_rk4_step(C.byref(g), _state(grid, u).reshape(-1), float(dt))
     if rc != 0:
         raise FloatingPointError("oracle rk4_step: non-physical state")
+    return u
+
+
+def ssprk3_step(grid: Grid, u, dt):
+    """SSP-RK3 (Shu & Osher 1988): an ablation of the classical RK4."""
+    g = grid.c()
+    rc = lib().orc_ssprk3_step(C.byref(g), _state(grid, u).reshape(-1), float(dt))
+    if rc != 0:
+        raise FloatingPointError("oracle ssprk3_step: non-physical state")
     return u
 
 

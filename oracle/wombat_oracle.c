@@ -789,6 +789,29 @@ int orc_rk4_step(const orc_grid *gr, double *u, double dt)
     return bad ? -1 : 0;
 }
 
+/* SSP-RK3 of Shu & Osher (1988), in its textbook convex-combination form:
+ *   u1 = u + dt L(u)
+ *   u2 = 3/4 u + 1/4 (u1 + dt L(u1))
+ *   u^{n+1} = 1/3 u + 2/3 (u2 + dt L(u2)). */
+int orc_ssprk3_step(const orc_grid *gr, double *u, double dt)
+{
+    long n = orc_state_size(gr), i;
+    double *u1 = (double *)malloc(sizeof(double) * n);
+    double *u2 = (double *)malloc(sizeof(double) * n);
+    double *k = (double *)calloc(n, sizeof(double));
+    int bad = 0;
+    memcpy(u1, u, sizeof(double) * n);
+    if (orc_rhs(gr, u1, k) != 0) bad = 1;               /* L(u) */
+    for (i = 0; i < n; ++i) u1[i] = u[i] + dt * k[i];
+    if (orc_rhs(gr, u1, k) != 0) bad = 1;
+    for (i = 0; i < n; ++i) u2[i] = 0.75 * u[i] + 0.25 * (u1[i] + dt * k[i]);
+    if (orc_rhs(gr, u2, k) != 0) bad = 1;
+    for (i = 0; i < n; ++i) u[i] = u[i] / 3.0 + 2.0 / 3.0 * (u2[i] + dt * k[i]);
+    orc_fill_ghosts(gr, u);
+    free(u1); free(u2); free(k);
+    return bad ? -1 : 0;
+}
+
 /* Neumaier-compensated sums of the 8 conserved variables over the interior. */
 void orc_sums(const orc_grid *gr, const double *u, double out[8])
 {

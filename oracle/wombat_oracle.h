@@ -84,6 +84,10 @@ int    orc_rhs_nofill(const orc_grid *g, const double *u, double *dudt);
 int    orc_rhs_linear(const orc_grid *g, const double *u, double *dudt);
 double orc_cfl_dt(const orc_grid *g, const double *u);
 int    orc_rk4_step(const orc_grid *g, double *u, double dt);
+/* Three-stage third-order strong-stability-preserving Runge-Kutta step
+ * (Shu & Osher 1988): an ablation of the classical RK4 of Sec. 2.1.
+ * Same contract as orc_rk4_step. */
+int    orc_ssprk3_step(const orc_grid *g, double *u, double dt);
 void   orc_sums(const orc_grid *g, const double *u, double out[8]);
 void   orc_divb(const orc_grid *g, const double *u, double *max_abs,
                 double *l1);

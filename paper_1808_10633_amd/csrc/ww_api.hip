@@ -106,6 +106,7 @@ int validate(const wombat_weno_config *c, std::string &why)
     if (!(c->eps > 0.0) || !std::isfinite(c->eps)) { why = "eps must be finite and > 0"; return WW_ERR_INVALID_ARG; }
     if (c->precision != WW_FP64 && c->precision != WW_FP32_MIXED) { why = "unknown precision"; return WW_ERR_INVALID_ARG; }
     if (c->weights != WW_WEIGHTS_JS && c->weights != WW_WEIGHTS_Z) { why = "unknown weights"; return WW_ERR_INVALID_ARG; }
+    if (c->integrator != WW_RK4 && c->integrator != WW_SSPRK3) { why = "unknown integrator"; return WW_ERR_INVALID_ARG; }
     bool user = false;
     for (int f = 0; f < 6; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
@@ -477,6 +478,8 @@ int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0, vo
 {
     int rc = precheck(ctx);
     if (rc) return rc;
+    if (ctx->cfg.integrator != WW_RK4)
+        return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "wombat_weno_stage runs the classical RK4 stages");
     if (s < 0 || s > 3) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "stage must be 0..3");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "dt must be finite and > 0");
     if (!d_us_in || !d_acc || !d_us_out || (s < 3 && !d_u0))
@@ -513,6 +516,30 @@ int rk4_stages(wombat_weno_t *ctx, void *d_u, double dt)
     return rc;
 }
 
+// The three stages of an SSP-RK3 step (Shu & Osher 1988); each writes
+// out = a0 u^n + a1 us + c dt L(us) (the update kernel's mode 2).
+int ssprk3_stages(wombat_weno_t *ctx, void *d_u, double dt)
+{
+    void *A = ctx->work[0], *B = ctx->work[1];
+    const ww::StageCoef k0{ 2, 0, 0.0, dt, 1.0, 0.0 };
+    const ww::StageCoef k1{ 2, 1, 0.0, 0.25 * dt, 0.75, 0.25 };
+    const ww::StageCoef k2{ 2, 2, 0.0, 2.0 / 3.0 * dt, 1.0 / 3.0, 2.0 / 3.0 };
+    DevGuard dg(ctx->cfg.device);
+    int rc;
+    if (ctx->cfg.precision == WW_FP64) {
+        double *u = (double *)d_u, *a = (double *)A, *b = (double *)B;
+        if (!(rc = operator_t<double>(ctx, u, u, nullptr, nullptr, a, k0)) &&
+            !(rc = operator_t<double>(ctx, a, u, a, nullptr, b, k1)))
+            rc = operator_t<double>(ctx, b, u, b, nullptr, u, k2);
+        return rc;
+    }
+    float *u = (float *)d_u, *a = (float *)A, *b = (float *)B;
+    if (!(rc = operator_t<float>(ctx, u, u, nullptr, nullptr, a, k0)) &&
+        !(rc = operator_t<float>(ctx, a, u, a, nullptr, b, k1)))
+        rc = operator_t<float>(ctx, b, u, b, nullptr, u, k2);
+    return rc;
+}
+
 }  // namespace
 
 int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used)
@@ -533,7 +560,11 @@ int wombat_weno_step(wombat_weno_t *ctx, void *d_u, double dt, double *dt_used)
         WW_CHECK(ctx, hipMemcpyAsync(ctx->backup, d_u, ctx->elems * ctx->esize, hipMemcpyDeviceToDevice,
                                      ctx->st));
     }
-    if ((rc = rk4_stages(ctx, d_u, dt))) return rc;
+    if (ctx->cfg.integrator == WW_SSPRK3) {
+        if ((rc = ssprk3_stages(ctx, d_u, dt))) return rc;
+    } else if ((rc = rk4_stages(ctx, d_u, dt))) {
+        return rc;
+    }
     if (guard) {
         DevGuard dg(ctx->cfg.device);
         int32_t bad = 0;
@@ -612,6 +643,8 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs on FP32 contexts");
     if (ctx->cfg.weights != WW_WEIGHTS_JS)
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router routes to the WENO-JS flux only");
+    if (ctx->cfg.integrator != WW_RK4)
+        return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs with the RK4 step only");
     if (!d_theta) { ctx->router = 0; return WW_OK; }
     if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
     if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");

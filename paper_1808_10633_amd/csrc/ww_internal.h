@@ -43,12 +43,17 @@ template <typename T>
 hipError_t launch_sweep(int dir, const T *u, T *flux, const Geom &G, const FaceBox &F,
                         const Phys &P, int weights, hipStream_t st);
 
-// mode 0: out = L(U); mode 1: RK stage (stage s, coefficients below).
+// mode 0: out = L(U); mode 1: low-storage classical RK4 stage s (acc and
+// out as below); mode 2: convex-combination stage of SSP-RK3,
+// out = a0 u0 + a1 us + cdt L(us), with us passed as acc_in (read only if
+// a1 != 0).
 struct StageCoef {
-    int mode;          // 0 rhs, 1 stage
+    int mode;          // 0 rhs, 1 RK4 stage, 2 SSP-RK3 stage
     int s;             // 0..3
-    double bdt;        // weight of L in acc
+    double bdt;        // weight of L in acc (mode 1)
     double cdt;        // weight of L in out
+    double a0 = 0.0;   // mode 2: weight of u0
+    double a1 = 0.0;   // mode 2: weight of us
 };
 template <typename T>
 hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const T *fx,

@@ -9,7 +9,8 @@
 //   field of each face advances by -(curl E)_n, and the cell-centred field by
 //   the mean of its two faces.  On an inactive axis the missing derivative
 //   vanishes and the EMF is the single available estimate.
-//   Then the low-storage classical RK4 update of the stage.
+//   Then the low-storage classical RK4 update of the stage, or a stage of
+//   SSP-RK3 (the integrator ablation).
 #pragma once
 #include "ww_internal.h"
 
@@ -85,6 +86,18 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
         return;
     }
     const T bdt = T(c.bdt), cdt = T(c.cdt);
+    if (c.mode == 2) {
+        const T a0 = T(c.a0), a1 = T(c.a1);
+        if (c.a1 != 0.0) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                a.out[id + v * sv] = a0 * a.u0[id + v * sv] + a1 * a.acc_in[id + v * sv] + cdt * L[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) a.out[id + v * sv] = a0 * a.u0[id + v * sv] + cdt * L[v];
+        }
+        return;
+    }
     if (c.s == 0) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) {

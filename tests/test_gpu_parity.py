@@ -182,6 +182,57 @@ def test_wenoz_refused_by_batched_and_learned_forms():
         ctx.set_router(theta, 0.5)
 
 
+# SSP-RK3 (the integrator ablation): steps against the oracle's textbook form
+@pytest.mark.parametrize("case,nsteps", [("brio_wu_1d", 10), ("turb_67x10x9", 5), ("smooth_13x70x11", 5)])
+def test_ssprk3_steps_parity(case, nsteps):
+    say(f"[SSP-RK3 steps] {case}, {nsteps} steps")
+    g, u = rhs_case(case)
+    ctx = ctx_for(g, integrator=W.SSPRK3)
+    ug = to_gpu(u)
+    ref = u.copy()
+    for step in range(nsteps):
+        dtg = ctx.cfl_dt(ug)
+        dto = O.cfl_dt(g, ref)
+        assert abs(dtg - dto) <= 1e-14 * dto
+        ctx.step(ug, dto)
+        O.ssprk3_step(g, ref, dto)
+    err, _ = scaled_state_error(g.interior(ug.cpu().numpy()), g.interior(ref))
+    rk4 = u.copy()
+    for _ in range(nsteps):
+        O.rk4_step(g, rk4, O.cfl_dt(g, rk4))
+    gap, _ = scaled_state_error(g.interior(rk4), g.interior(ref))
+    say(f"  scaled state error {err:.3e} (RK4 vs SSP-RK3 in the oracle: {gap:.3e})")
+    assert err < TOL
+    assert gap > 1e3 * TOL
+
+
+def test_ssprk3_fp32_steps_against_oracle():
+    n = 24
+    say("[SSP-RK3 fp32] 24^3 turbulence, 5 steps vs oracle")
+    g = O.Grid(n, n, n, 1 / n, 1 / n, 1 / n)
+    u = I.turbulence((n, n, n), mach=1.0, beta=100.0, seed=77, kmax=8).numpy().copy()
+    ctx = W.Context(n, n, n, precision=W.WW_FP32_MIXED, integrator=W.SSPRK3)
+    ug = torch.from_numpy(u).cuda().float()
+    ref = u.copy()
+    for _ in range(5):
+        dt = O.cfl_dt(g, ref)
+        ctx.step(ug, dt)
+        O.ssprk3_step(g, ref, dt)
+    err, _ = scaled_state_error(g.interior(ug.double().cpu().numpy()), g.interior(ref))
+    say(f"  fp32 scaled state error {err:.3e}")
+    assert err < 1e-5
+
+
+def test_ssprk3_refused_by_stage_call_and_router():
+    ctx = W.Context(16, 16, 16, precision=W.WW_FP32_MIXED, integrator=W.SSPRK3)
+    u = ctx.new_state()
+    with pytest.raises(W.WenoError, match="RK4"):
+        ctx.stage(0, 0.01, u, u, torch.zeros_like(u), torch.zeros_like(u))
+    theta = torch.zeros(W.mlp_param_count(), dtype=torch.float32, device="cuda")
+    with pytest.raises(W.WenoError, match="RK4"):
+        ctx.set_router(theta, 0.5)
+
+
 def test_alfven_wave_32cube_10_steps_every_step():
     """The spec case: inclined Alfven wave, 32^3, CFL 0.4, 10 steps."""
     n = 32
