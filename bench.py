@@ -329,13 +329,15 @@ def learned_form(a, wombat, inputs, router):
     return res
 
 
-ABLATIONS = (("rk4_js", "WEIGHTS_JS", "RK4"), ("rk4_z", "WEIGHTS_Z", "RK4"), ("ssprk3_js", "WEIGHTS_JS", "SSPRK3"))
+ABLATIONS = (("rk4_js", "WEIGHTS_JS", "RK4", "LF_LOCAL"), ("rk4_z", "WEIGHTS_Z", "RK4", "LF_LOCAL"),
+             ("ssprk3_js", "WEIGHTS_JS", "SSPRK3", "LF_LOCAL"), ("rk4_js_global_lf", "WEIGHTS_JS", "RK4", "LF_GLOBAL"))
 
 
 def ablation(a, wombat, inputs):
     """Scheme variants on the single-grid operator: the paper's choice
-    (weights of eq. (3), classical RK4), WENO-Z weights (Borges et al. 2008,
-    exponent 1) and SSP-RK3 (Shu & Osher 1988).  Cost: timed steps and
+    (weights of eq. (3), classical RK4, per-stencil LF speeds), WENO-Z weights
+    (Borges et al. 2008, exponent 1), SSP-RK3 (Shu & Osher 1988) and global
+    LF speeds per sweep.  Cost: timed steps and
     event-timed kernels at n^3 on the rms-Mach-1 turbulence of the default
     line, both precisions.  Robustness (FP64): the shocked turbulence recipe
     (beta 10, 10 % compressive, log-normal density sigma 0.5, seed 6000) at
@@ -347,10 +349,10 @@ def ablation(a, wombat, inputs):
     cost = {}
     for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
         P = wombat.WW_FP64 if prec == "fp64" else wombat.WW_FP32_MIXED
-        for name, wk, ik in ABLATIONS:
+        for name, wk, ik, lk in ABLATIONS:
             u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda").to(dt_).contiguous()
             ctx = wombat.Context(n, n, n, precision=P, cfl=0.4, weights=getattr(wombat, wk),
-                                 integrator=getattr(wombat, ik))
+                                 integrator=getattr(wombat, ik), lf_speed=getattr(wombat, lk))
             for _ in range(a.warmup):
                 ctx.step(u, 0.0)
             torch.cuda.synchronize()
@@ -373,11 +375,11 @@ def ablation(a, wombat, inputs):
     for m in (3.0, 6.0, 10.0):
         for e in (64, 128, 256):
             row = {"precision": "fp64", "mach": m, "n": e}
-            for name, wk, ik in ABLATIONS:
+            for name, wk, ik, lk in ABLATIONS:
                 u = inputs.turbulence((e, e, e), mach=m, beta=10.0, seed=6000, compressive_fraction=0.1,
                                       lognormal_sigma=0.5, device="cuda").contiguous()
                 ctx = wombat.Context(e, e, e, precision=wombat.WW_FP64, cfl=0.4, weights=getattr(wombat, wk),
-                                     integrator=getattr(wombat, ik))
+                                     integrator=getattr(wombat, ik), lf_speed=getattr(wombat, lk))
                 t, s, fail = 0.0, 0, None
                 while s < a.abl_steps:
                     s += 1
@@ -391,7 +393,7 @@ def ablation(a, wombat, inputs):
                 row[name] = {"failed_at_step": fail, "t_reached": t, "steps": s}
                 del ctx, u
             print(f"[bench] ablation Mach {m:g} {e}^3: " +
-                  ", ".join(f"{k} {row[k]['failed_at_step']} (t {row[k]['t_reached']:.5f})" for k, _, _ in ABLATIONS),
+                  ", ".join(f"{k} {row[k]['failed_at_step']} (t {row[k]['t_reached']:.5f})" for k, *_ in ABLATIONS),
                   file=sys.stderr, flush=True)
             runs.append(row)
             torch.cuda.empty_cache()

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define WOMBAT_WENO_ABI_VERSION 3
+#define WOMBAT_WENO_ABI_VERSION 4
 
 typedef enum {
     WW_OK = 0,
@@ -84,6 +84,13 @@ typedef enum { WW_WEIGHTS_JS = 0, WW_WEIGHTS_Z = 1 } ww_weights;
  * u^{n+1} = 1/3 u + 2/3 (u2 + dt L(u2)); an ablation of the paper's
  * choice, single-grid operator and wombat_weno_step only. */
 typedef enum { WW_RK4 = 0, WW_SSPRK3 = 1 } ww_integrator;
+/* Lax-Friedrichs speed alpha^s of eq. (1).  WW_LF_LOCAL: per interface, the
+ * largest |lambda^s| of field s over its six stencil cells (the reading of
+ * the paper's "simple Lax-Friedrichs splitting" used throughout).
+ * WW_LF_GLOBAL: per sweep direction and stage, the largest |lambda^s| over
+ * every cell the sweep reads (one extra FP64 reduction pass per direction
+ * and stage); an ablation, single-grid operator only. */
+typedef enum { WW_LF_LOCAL = 0, WW_LF_GLOBAL = 1 } ww_lf_speed;
 typedef enum { WW_BC_PERIODIC = 0, WW_BC_OUTFLOW = 1, WW_BC_USER = 2 } ww_bc;
 
 /* User boundary hook: called for each WW_BC_USER face (0..5 = -x,+x,-y,+y,
@@ -113,6 +120,8 @@ typedef struct {
     int integrator;          /* ww_integrator (added in ABI 3); the batched
                                 and learned forms and wombat_weno_stage accept
                                 WW_RK4 only                                   */
+    int lf_speed;            /* ww_lf_speed (added in ABI 4); the batched and
+                                learned forms accept WW_LF_LOCAL only          */
 } wombat_weno_config;
 
 typedef struct wombat_weno wombat_weno_t;
@@ -122,7 +131,7 @@ int wombat_weno_abi_version(void);
 
 /* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
  * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0,
- * WW_WEIGHTS_JS, WW_RK4.
+ * WW_WEIGHTS_JS, WW_RK4, WW_LF_LOCAL.
  * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
 int wombat_weno_config_default(wombat_weno_config *cfg);
 

@@ -39,7 +39,7 @@ class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("eps", C.c_double),
-                ("bc", C.c_int * 6), ("weights", C.c_int)]
+                ("bc", C.c_int * 6), ("weights", C.c_int), ("lf_global", C.c_int)]
 
 
 @dataclass
@@ -56,6 +56,7 @@ class Grid:
     eps: float = 1e-6
     bc: tuple = field(default_factory=lambda: (0, 0, 0, 0, 0, 0))   # 0 periodic, 1 outflow
     weights: int = 0          # 0: weights of eq. (3); 1: WENO-Z (ablation)
+    lf_global: int = 0        # 0: LF speed per stencil; 1: per sweep over the box (ablation)
 
     def c(self) -> _Grid:
         g = _Grid(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
@@ -63,6 +64,7 @@ class Grid:
         for i in range(6):
             g.bc[i] = int(self.bc[i])
         g.weights = int(self.weights)
+        g.lf_global = int(self.lf_global)
         return g
 
     @property
@@ -122,6 +124,8 @@ def lib():
         L.orc_rk4_step.restype = C.c_int
         L.orc_ssprk3_step.argtypes = [g, _dp, d]
         L.orc_ssprk3_step.restype = C.c_int
+        L.orc_lf_global.argtypes = [g, _dp, C.c_int, _dp]
+        L.orc_interface_flux_alpha.argtypes = [_dp, d, d, C.c_int, _dp, _dp]
         L.orc_sums.argtypes = [g, _dp, _dp]
         L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
         _lib = L
@@ -313,6 +317,22 @@ def ssprk3_step(grid: Grid, u, dt):
     if rc != 0:
         raise FloatingPointError("oracle ssprk3_step: non-physical state")
     return u
+
+
+def lf_global(grid: Grid, u, d):
+    """Global LF speeds (7 fields) of the d-sweep of a state with filled
+    ghosts (ablation of the per-stencil speed)."""
+    out = np.zeros(7)
+    lib().orc_lf_global(C.byref(grid.c()), _state(grid, u).reshape(-1), int(d), out)
+    return out
+
+
+def interface_flux_alpha(Us, alpha, gamma=5.0 / 3.0, eps=1e-6, z=0):
+    """The characteristic flux of a 6x8 sweep-frame stencil with given LF
+    speeds per field (ablation)."""
+    F = np.zeros(8)
+    lib().orc_interface_flux_alpha(_f64(Us).reshape(-1), gamma, eps, int(z), _f64(alpha), F)
+    return F
 
 
 def sums(grid: Grid, u):

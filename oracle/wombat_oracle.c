@@ -400,22 +400,31 @@ static double weight_deviation(const double f[6], const double u[6], double alph
  * receives the largest deviation of any weight of any field from the linear
  * weights -- the label of a troubled interface. */
 static void interface_flux_mode(int z, const double Us[48], double gamma, double eps,
-                                int common_alpha, double Fhat[8], double *dev);
+                                int common_alpha, const double *alpha_g, double Fhat[8],
+                                double *dev);
 
 void orc_interface_flux_ex(const double Us[48], double gamma, double eps,
                            int common_alpha, double Fhat[8], double *dev)
 {
-    interface_flux_mode(0, Us, gamma, eps, common_alpha, Fhat, dev);
+    interface_flux_mode(0, Us, gamma, eps, common_alpha, NULL, Fhat, dev);
 }
 
 /* The characteristic flux with the WENO-Z weights (ablation). */
 void orc_interface_flux_z(const double Us[48], double gamma, double eps, double Fhat[8])
 {
-    interface_flux_mode(1, Us, gamma, eps, 0, Fhat, NULL);
+    interface_flux_mode(1, Us, gamma, eps, 0, NULL, Fhat, NULL);
+}
+
+/* The characteristic flux with given per-field LF speeds (ablation). */
+void orc_interface_flux_alpha(const double Us[48], double gamma, double eps, int z,
+                              const double alpha[7], double Fhat[8])
+{
+    interface_flux_mode(z, Us, gamma, eps, 0, alpha, Fhat, NULL);
 }
 
 static void interface_flux_mode(int z, const double Us[48], double gamma, double eps,
-                                int common_alpha, double Fhat[8], double *dev)
+                                int common_alpha, const double *alpha_g, double Fhat[8],
+                                double *dev)
 {
     double F[6][8], lamc[6][8], W[6][8], Wm[8], lam[8], L[64], R[64], Fs[8];
     int j, c, s;
@@ -451,6 +460,7 @@ static void interface_flux_mode(int z, const double Us[48], double gamma, double
             if (fabs(lamc[j][s]) > alpha) alpha = fabs(lamc[j][s]);
         }
         if (common_alpha && s < 7) alpha = acommon;   /* the B_n identity row keeps 0 */
+        if (alpha_g && s < 7) alpha = alpha_g[s];
         Fs[s] = field_flux_mode(z, fs, us, alpha, eps);
         if (dev && s < 7) {
             double dv = weight_deviation(fs, us, alpha, eps);
@@ -632,6 +642,36 @@ static int nonphysical(const double U[8], double gamma)
 
 /* L(U): the semi-discrete right-hand side of one Runge-Kutta stage.
  * Returns 0, or -1 if a stencil cell is non-physical (rho<=0 or p<=0). */
+/* Global LF speeds of the d-sweep (ablation of the per-stencil speed): the
+ * cells are those the sweep's stencils read; u must hold filled ghosts. */
+void orc_lf_global(const orc_grid *gr, const double *u, int d, double alpha[7])
+{
+    geom G = mkgeom(gr);
+    int lo[3], hi[3], e, c, pos[3];
+    int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    int perm[8] = { RHO, MX + d, MX + t1, MX + t2, BX + d, BX + t1, BX + t2, EN };
+    for (e = 0; e < 3; ++e) {
+        if (e == d) { lo[e] = -3; hi[e] = G.n[e] + 3; }
+        else if (active(&G, e)) { lo[e] = -1; hi[e] = G.n[e] + 1; }
+        else { lo[e] = 0; hi[e] = 1; }
+    }
+    for (c = 0; c < 7; ++c) alpha[c] = 0.0;
+    for (pos[2] = lo[2]; pos[2] < hi[2]; ++pos[2])
+    for (pos[1] = lo[1]; pos[1] < hi[1]; ++pos[1])
+    for (pos[0] = lo[0]; pos[0] < hi[0]; ++pos[0]) {
+        double U[8], W[8], cf, ca, cs;
+        long id = cidx(&G, pos[0], pos[1], pos[2]);
+        for (c = 0; c < 8; ++c) U[c] = u[perm[c] * G.sv + id];
+        if (nonphysical(U, gr->gamma)) continue;      /* reported by the sweep itself */
+        orc_cons_to_prim(U, gr->gamma, W);
+        orc_wave_speeds(U, 0, gr->gamma, &cf, &ca, &cs);
+        double vn = W[1];
+        double lam[7] = { vn - cf, vn - ca, vn - cs, vn, vn + cs, vn + ca, vn + cf };
+        for (c = 0; c < 7; ++c)
+            if (fabs(lam[c]) > alpha[c]) alpha[c] = fabs(lam[c]);
+    }
+}
+
 static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fill, int linear)
 {
     geom G = mkgeom(gr);
@@ -662,6 +702,8 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
         int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
         int perm[8] = { RHO, MX + d, MX + t1, MX + t2, BX + d, BX + t1, BX + t2, EN };
         int pos[3];
+        double ag[7] = { 0, 0, 0, 0, 0, 0, 0 };
+        if (gr->lf_global) orc_lf_global(gr, u, d, ag);
         for (pos[2] = FF[d].lo[2]; pos[2] < FF[d].lo[2] + FF[d].cnt[2]; ++pos[2])
         for (pos[1] = FF[d].lo[1]; pos[1] < FF[d].lo[1] + FF[d].cnt[1]; ++pos[1])
         for (pos[0] = FF[d].lo[0]; pos[0] < FF[d].lo[0] + FF[d].cnt[0]; ++pos[0]) {
@@ -675,6 +717,7 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
                 if (nonphysical(Us + 8 * j, gr->gamma)) bad = 1;
             }
             if (linear) orc_linear_flux(Us, gr->gamma, Fh);
+            else if (gr->lf_global) orc_interface_flux_alpha(Us, gr->gamma, gr->eps, gr->weights, ag, Fh);
             else if (gr->weights) orc_interface_flux_z(Us, gr->gamma, gr->eps, Fh);
             else orc_interface_flux(Us, gr->gamma, gr->eps, Fh);
             long fi = fidx(&FF[d], pos[0], pos[1], pos[2]);

@@ -35,6 +35,8 @@ typedef struct {
     double eps;            /* WENO epsilon (the paper's value is 1e-6)         */
     int bc[6];             /* faces -x,+x,-y,+y,-z,+z: 0 periodic, 1 outflow   */
     int weights;           /* 0: weights of eq. (3); 1: WENO-Z (ablation)      */
+    int lf_global;         /* 0: LF speed per stencil; 1: per sweep over the
+                              whole box (ablation)                             */
 } orc_grid;
 
 /* ---- scalar WENO5 pieces (Sec. 2.1, eqs. 1-7) ---- */
@@ -45,6 +47,14 @@ double orc_weno_phi(double a, double b, double c, double d, double eps);
 void   orc_weno_weights_z(double a, double b, double c, double d, double eps,
                           double omega[3], double is[3]);
 void   orc_interface_flux_z(const double Us[48], double gamma, double eps, double Fhat[8]);
+/* The characteristic flux with given LF speeds alpha[0..6], one per field
+ * (ablation: the global speeds of a sweep); z selects the WENO-Z weights. */
+void   orc_interface_flux_alpha(const double Us[48], double gamma, double eps, int z,
+                                const double alpha[7], double Fhat[8]);
+/* Global LF speeds of the d-sweep: per field, the largest |lambda^s| over
+ * every cell a stencil of that sweep reads (the 3-deep ghosts along d, one
+ * transverse ghost layer on active transverse axes). */
+void   orc_lf_global(const orc_grid *g, const double *u, int d, double alpha[7]);
 double orc_weno_field_flux(const double f[6], const double u[6],
                            double alpha, double eps);
 /* eq. (1) for one field with the WENO-Z weights (ablation). */

@@ -42,6 +42,7 @@ struct wombat_weno {
     unsigned char *rmask;  // routing decisions per face, the three directions one after another
     int router_reuse;      // stages 2-4 of a step: reuse the decisions of its first stage
     int64_t fallbacks;     // routed steps redone with full WENO
+    double *lfg;           // global LF speeds: partials, then 7 per direction (WW_LF_GLOBAL only)
     hipStream_t st;
     int sticky;            // a HIP error happened: every later call fails
     std::string err;
@@ -107,6 +108,7 @@ int validate(const wombat_weno_config *c, std::string &why)
     if (c->precision != WW_FP64 && c->precision != WW_FP32_MIXED) { why = "unknown precision"; return WW_ERR_INVALID_ARG; }
     if (c->weights != WW_WEIGHTS_JS && c->weights != WW_WEIGHTS_Z) { why = "unknown weights"; return WW_ERR_INVALID_ARG; }
     if (c->integrator != WW_RK4 && c->integrator != WW_SSPRK3) { why = "unknown integrator"; return WW_ERR_INVALID_ARG; }
+    if (c->lf_speed != WW_LF_LOCAL && c->lf_speed != WW_LF_GLOBAL) { why = "unknown lf_speed"; return WW_ERR_INVALID_ARG; }
     bool user = false;
     for (int f = 0; f < 6; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
@@ -187,6 +189,7 @@ void release(wombat_weno_t *c)
     if (c->queue) (void)hipFree(c->queue);
     if (c->rmask) (void)hipFree(c->rmask);
     if (c->qcount) (void)hipFree(c->qcount);
+    if (c->lfg) (void)hipFree(c->lfg);
     for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
@@ -225,6 +228,12 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
     int rc = fill_ghosts_t<T>(c, us);
     if (rc) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
+    if (c->lfg) {
+        // global LF speeds of the three sweeps, from this stage's state
+        for (int d = 0; d < 3; ++d)
+            WW_CHECK(c, ww::launch_lf_global<T>(us, c->G, d, c->cfg.gamma, c->lfg,
+                                                c->lfg + ww::LF_PART_DOUBLES + 7 * d, c->st));
+    }
     if (c->router && c->router_force > 0) {
         // all interfaces full: the plain sweep (same face arithmetic); no smooth ones
         const long tot = c->nsm_blocks[0] + c->nsm_blocks[1] + c->nsm_blocks[2];
@@ -246,6 +255,7 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
                 continue;
             }
         }
+        if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
         WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
     }
     WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, (const T *)c->ff[0],
@@ -269,6 +279,10 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
     if (rc) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
     ww::StageCoef k{ 0, 0, 0.0, 0.0 };
+    if (c->lfg)      // the global LF speeds, once, outside the timed launches
+        for (int d = 0; d < 3; ++d)
+            WW_CHECK(c, ww::launch_lf_global<T>(u, c->G, d, c->cfg.gamma, c->lfg,
+                                                c->lfg + ww::LF_PART_DOUBLES + 7 * d, c->st));
     for (int which = 0; which < 5; ++which) {
         ms[which] = 0.0;
         if (which >= 1 && which <= 3 && !c->G.act[which - 1]) continue;
@@ -280,6 +294,7 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
                     WW_CHECK(c, ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
             } else if (which <= 3) {
                 int d = which - 1;
+                if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
                 WW_CHECK(c, ww::launch_sweep<T>(d, u, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
             } else {
                 WW_CHECK(c, ww::launch_update<T>(nullptr, nullptr, nullptr, (T *)c->work[0],
@@ -361,6 +376,9 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
     if (dev_alloc((void **)&c->part, sizeof(double) * 8 * c->nblk) != hipSuccess) return oom("partials");
     if (dev_alloc((void **)&c->partflag, sizeof(int32_t) * c->nblk) != hipSuccess) return oom("flags");
     if (dev_alloc((void **)&c->dsmall, sizeof(double) * 20) != hipSuccess) return oom("results");
+    if (cfg->lf_speed == WW_LF_GLOBAL &&
+        dev_alloc((void **)&c->lfg, sizeof(double) * (ww::LF_PART_DOUBLES + 21)) != hipSuccess)
+        return oom("global LF speeds");
     c->dflag = (int32_t *)(c->dsmall + 16);
     if (hipHostMalloc((void **)&c->hsmall, sizeof(double) * 20, hipHostMallocDefault) != hipSuccess) {
         c->hsmall = nullptr;
@@ -645,6 +663,8 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router routes to the WENO-JS flux only");
     if (ctx->cfg.integrator != WW_RK4)
         return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router runs with the RK4 step only");
+    if (ctx->cfg.lf_speed != WW_LF_LOCAL)
+        return fail_ctx(ctx, WW_ERR_UNSUPPORTED, "the learned router uses the per-stencil LF speeds only");
     if (!d_theta) { ctx->router = 0; return WW_OK; }
     if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
     if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");

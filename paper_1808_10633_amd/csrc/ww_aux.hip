@@ -6,6 +6,8 @@
 // axes) so that edges and corners are consistent.
 // CFL: dt = C / max over interior cells of sum_d (|v_d| + c_f,d)/dx_d, in
 // FP64, with a count of non-physical cells (rho <= 0, p <= 0, non-finite).
+// Global LF speeds (an ablation of the per-stencil speed): per sweep
+// direction and field, the largest |lambda^s| over the sweep's cells.
 // Reductions are two-pass (per-block partials, then one block) with a fixed
 // assignment of cells to threads and a fixed tree: results are bitwise
 // reproducible.  No floating-point atomics.
@@ -130,6 +132,71 @@ __global__ __launch_bounds__(RB) void cfl_final(const double *part, const int32_
     }
 }
 
+// Global LF speeds of the d-sweep: per-block maxima of the seven |lambda^s|
+// over a fixed grid-stride assignment of the sweep's cell set.
+template <typename T>
+__global__ __launch_bounds__(RB) void lf_partial(const T *__restrict__ u, Geom G, int d, double gamma,
+                                                 double *part)
+{
+    int lo[3], cnt[3];
+    for (int e = 0; e < 3; ++e) {
+        if (e == d) { lo[e] = -G.g[e]; cnt[e] = G.n[e] + 2 * G.g[e]; }
+        else if (G.act[e]) { lo[e] = -1; cnt[e] = G.n[e] + 2; }
+        else { lo[e] = 0; cnt[e] = 1; }
+    }
+    const long total = (long)cnt[0] * cnt[1] * cnt[2];
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    double m[7] = { 0, 0, 0, 0, 0, 0, 0 };
+    for (long c = (long)blockIdx.x * RB + threadIdx.x; c < total; c += (long)gridDim.x * RB) {
+        const int p0 = lo[0] + (int)(c % cnt[0]);
+        const int p1 = lo[1] + (int)((c / cnt[0]) % cnt[1]);
+        const int p2 = lo[2] + (int)(c / ((long)cnt[0] * cnt[1]));
+        const long id = G.base + p0 * G.s[0] + p1 * G.s[1] + (long)p2 * G.s[2];
+        double q[8];
+        bool fin = true;
+        for (int v = 0; v < 8; ++v) { q[v] = (double)u[id + v * G.sv]; fin = fin && isfinite(q[v]); }
+        const double r = q[0];
+        const double ir = 1.0 / r;
+        const double b2 = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+        const double pr = (gamma - 1.0) * (q[7] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ir - 0.5 * b2);
+        if (!fin || !(r > 0.0) || !(pr > 0.0)) continue;
+        const double vn = q[1 + d] * ir;
+        const double a2 = gamma * pr * ir;
+        const double bn2 = q[4 + d] * q[4 + d] * ir;
+        double bt2 = (q[4 + t1] * q[4 + t1] + q[4 + t2] * q[4 + t2]) * ir;
+        const double dd = a2 - bn2;
+        const double cf2 = 0.5 * (a2 + bn2 + bt2 + sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2)));
+        const double cf = sqrt(cf2), cs = sqrt(a2 * bn2 / cf2), ca = sqrt(bn2);
+        const double lam[7] = { vn - cf, vn - ca, vn - cs, vn, vn + cs, vn + ca, vn + cf };
+        for (int k = 0; k < 7; ++k) m[k] = fmax(m[k], fabs(lam[k]));
+    }
+    __shared__ double sm[7][RB];
+    for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = m[k];
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[7 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(RB) void lf_final(const double *part, int nblk, double *out)
+{
+    __shared__ double sm[7][RB];
+    double m[7] = { 0, 0, 0, 0, 0, 0, 0 };
+    for (int b = threadIdx.x; b < nblk; b += RB)
+        for (int k = 0; k < 7; ++k) m[k] = fmax(m[k], part[7 * b + k]);
+    for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = m[k];
+    __syncthreads();
+    for (int h = RB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[threadIdx.x] = sm[threadIdx.x][0];
+}
+
 template <typename T>
 __global__ __launch_bounds__(RB) void sums_partial(const T *__restrict__ u, Geom G, double *part)
 {
@@ -250,6 +317,23 @@ hipError_t launch_cfl(const T *u, const Geom &G, double gamma, double cfl, doubl
 }
 
 template <typename T>
+hipError_t launch_lf_global(const T *u, const Geom &G, int d, double gamma, double *part, double *d_out,
+                            hipStream_t st)
+{
+    if (!G.act[d]) return hipSuccess;
+    long total = 1;
+    for (int e = 0; e < 3; ++e)
+        total *= (e == d) ? G.n[e] + 2 * G.g[e] : (G.act[e] ? G.n[e] + 2 : 1);
+    const long b = (total + RB - 1) / RB;
+    const int nblk = (int)(b < LF_BLOCKS ? b : LF_BLOCKS);
+    hipLaunchKernelGGL((lf_partial<T>), dim3(nblk), dim3(RB), 0, st, u, G, d, gamma, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lf_final, dim3(1), dim3(RB), 0, st, part, nblk, d_out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_sums(const T *u, const Geom &G, double *part, int nblk, double *d_out,
                        hipStream_t st)
 {
@@ -279,7 +363,9 @@ hipError_t launch_divb(const T *u, const Geom &G, double *part, int nblk, double
     template hipError_t launch_sums<T>(const T *, const Geom &, double *, int, double *,      \
                                        hipStream_t);                                         \
     template hipError_t launch_divb<T>(const T *, const Geom &, double *, int, double *,      \
-                                       hipStream_t);
+                                       hipStream_t);                                         \
+    template hipError_t launch_lf_global<T>(const T *, const Geom &, int, double, double *,   \
+                                            double *, hipStream_t);
 WW_INST(double)
 WW_INST(float)
 

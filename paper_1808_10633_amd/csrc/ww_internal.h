@@ -34,6 +34,7 @@ constexpr int NFC = 7;   // stored face-flux components
 struct Phys {
     double gamma, eps;
     double igm1;       // 1 / (gamma - 1)
+    const double *ag = nullptr;   // global LF speeds of this sweep (7 fields), or null
 };
 
 // Launchers (return the hipError_t of the launch).
@@ -69,6 +70,17 @@ hipError_t launch_cfl(const T *u, const Geom &G, double gamma, double cfl, doubl
                       int32_t *partflag, int nblk, double *d_dt, int32_t *d_flag,
                       hipStream_t st);
 int cfl_blocks(const Geom &G);
+
+// Global LF speeds of the d-sweep (the LF-speed ablation): per field, the
+// largest |lambda^s| over the cells the sweep's stencils read (3-deep ghosts
+// along d, one transverse ghost layer on active transverse axes), in FP64;
+// non-physical cells are skipped (the CFL reduction reports them).  part
+// holds LF_PART_DOUBLES; d_out receives 7 doubles.
+constexpr int LF_BLOCKS = 1024;
+constexpr long LF_PART_DOUBLES = 7L * LF_BLOCKS;
+template <typename T>
+hipError_t launch_lf_global(const T *u, const Geom &G, int d, double gamma, double *part, double *d_out,
+                            hipStream_t st);
 
 template <typename T>
 hipError_t launch_sums(const T *u, const Geom &G, double *part, int nblk, double *d_out,

@@ -11,20 +11,20 @@ namespace {
 // lane to scratch instead.  The WENO-JS and FP32 code is unchanged by it.
 #define WW_TWO_WAVES __attribute__((amdgpu_waves_per_eu(2)))
 
-template <int DIR, int FT, typename T, bool WZ>
+template <int DIR, int FT, typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_kernel(const T *__restrict__ u, T *__restrict__ flux,
                                                      Geom G, FaceBox F, Phys P)
 {
     __shared__ T sq[sw::NQ * sw::tile_cells<DIR, FT>()];
-    sw::sweep_tile<DIR, FT, T, WZ>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
+    sw::sweep_tile<DIR, FT, T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
 }
 
-template <typename T, bool WZ>
+template <typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xseg_kernel(const T *__restrict__ u, T *__restrict__ flux,
                                                          Geom G, FaceBox F, Phys P)
 {
     __shared__ T sq[sw::NQ * sw::ROWS * sw::NCX];
-    sw::sweep_tile_xseg<T, WZ>(u, flux, G, F, P, blockIdx.x, sq);
+    sw::sweep_tile_xseg<T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, sq);
 }
 
 // FP64 y/z sweeps: 32 positions x 8 faces per tile (1.6 staged cells per
@@ -32,15 +32,15 @@ __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xseg_kernel(const T *_
 // 512^3.  FP32 keeps 64 positions x 8 faces (sweep_tile, FT = 8).
 constexpr int YZ_PW_F64 = 32;
 
-template <int DIR, int PW, typename T, bool WZ>
+template <int DIR, int PW, typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_yz_kernel(const T *__restrict__ u, T *__restrict__ flux,
                                                        Geom G, FaceBox F, Phys P)
 {
     __shared__ T sq[sw::NQ * sw::yz_cells<PW>()];
-    sw::sweep_tile_yz<DIR, PW, T, WZ>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
+    sw::sweep_tile_yz<DIR, PW, T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
 }
 
-template <int DIR, int FT, typename T, bool WZ>
+template <int DIR, int FT, typename T, bool WZ, bool GLF>
 hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
                       hipStream_t st)
 {
@@ -48,7 +48,7 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
         constexpr int PW = YZ_PW_F64, B = (DIR == 1) ? 2 : 1;
         const long npos = (long)F.cnt[0] * F.cnt[B];
         const long na = (npos + PW - 1) / PW, nb = (F.cnt[DIR] + 256 / PW - 1) / (256 / PW);
-        hipLaunchKernelGGL((sweep_yz_kernel<DIR == 0 ? 1 : DIR, PW, T, WZ>), dim3((unsigned)na, (unsigned)nb),
+        hipLaunchKernelGGL((sweep_yz_kernel<DIR == 0 ? 1 : DIR, PW, T, WZ, GLF>), dim3((unsigned)na, (unsigned)nb),
                            dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P);
         return hipGetLastError();
     }
@@ -56,13 +56,13 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
         // long rows: flattened face segments, no ragged tile per row
         const long total = (long)F.cnt[0] * F.cnt[1] * F.cnt[2];
         const long nt = (total + sw::TILE * sw::ROWS - 1) / (sw::TILE * sw::ROWS);
-        hipLaunchKernelGGL((sweep_xseg_kernel<T, WZ>), dim3((unsigned)nt), dim3(sw::TILE, sw::ROWS), 0, st,
+        hipLaunchKernelGGL((sweep_xseg_kernel<T, WZ, GLF>), dim3((unsigned)nt), dim3(sw::TILE, sw::ROWS), 0, st,
                            u, flux, G, F, P);
         return hipGetLastError();
     }
     long na, nb;
     sw::sweep_tiles<DIR, FT>(F, na, nb);
-    hipLaunchKernelGGL((sweep_kernel<DIR, FT, T, WZ>), dim3((unsigned)na, (unsigned)nb),
+    hipLaunchKernelGGL((sweep_kernel<DIR, FT, T, WZ, GLF>), dim3((unsigned)na, (unsigned)nb),
                        dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P);
     return hipGetLastError();
 }
@@ -70,25 +70,29 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
 // faces per y/z tile of the FP32 sweep (FP64 y/z sweeps use sweep_yz_kernel)
 template <typename T> constexpr int ft_of() { return sizeof(T) == 8 ? 4 : 8; }
 
+template <typename T, bool WZ, bool GLF>
+hipError_t launch_dirs(int dir, const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
+                       hipStream_t st)
+{
+    constexpr int FT = ft_of<T>();
+    switch (dir) {
+    case 0: return launch_dir<0, FT, T, WZ, GLF>(u, flux, G, F, P, st);
+    case 1: return launch_dir<1, FT, T, WZ, GLF>(u, flux, G, F, P, st);
+    default: return launch_dir<2, FT, T, WZ, GLF>(u, flux, G, F, P, st);
+    }
+}
+
 }  // namespace
 
 template <typename T>
 hipError_t launch_sweep(int dir, const T *u, T *flux, const Geom &G, const FaceBox &F,
                         const Phys &P, int weights, hipStream_t st)
 {
-    constexpr int FT = ft_of<T>();
-    if (weights == WEIGHTS_Z) {
-        switch (dir) {
-        case 0: return launch_dir<0, FT, T, true>(u, flux, G, F, P, st);
-        case 1: return launch_dir<1, FT, T, true>(u, flux, G, F, P, st);
-        default: return launch_dir<2, FT, T, true>(u, flux, G, F, P, st);
-        }
-    }
-    switch (dir) {
-    case 0: return launch_dir<0, FT, T, false>(u, flux, G, F, P, st);
-    case 1: return launch_dir<1, FT, T, false>(u, flux, G, F, P, st);
-    default: return launch_dir<2, FT, T, false>(u, flux, G, F, P, st);
-    }
+    const bool z = weights == WEIGHTS_Z, glf = P.ag != nullptr;
+    if (z && glf) return launch_dirs<T, true, true>(dir, u, flux, G, F, P, st);
+    if (z) return launch_dirs<T, true, false>(dir, u, flux, G, F, P, st);
+    if (glf) return launch_dirs<T, false, true>(dir, u, flux, G, F, P, st);
+    return launch_dirs<T, false, false>(dir, u, flux, G, F, P, st);
 }
 
 template hipError_t launch_sweep<double>(int, const double *, double *, const Geom &,

@@ -161,10 +161,12 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // out: sweep-frame flux (rho, mn, mt1, mt2, Bt1, Bt2, E).
 // LBL: also return in *dev the largest deviation of any weight of any field
 // from the linear weights (the label of a troubled interface).
-template <typename T, bool LBL = false, bool WZ = false>
+// GLF: the LF speed of field s is ag[s] (global speeds of the sweep, an
+// ablation) instead of the largest |lambda^s| over the six cells.
+template <typename T, bool LBL = false, bool WZ = false, bool GLF = false>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
                                           double gamma, double igm1, T eps, T (&out)[7],
-                                          T *dev = nullptr)
+                                          T *dev = nullptr, const double *ag = nullptr)
 {
 #define QQ(q, j) sq[(q) * qs + off + (j) * cstr]
     T C[7], dY[5][7], dZ[5][7], am[7];
@@ -192,6 +194,10 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
             Fp[c] = Fj[c];
             Up[c] = Uj[c];
         }
+    }
+    if constexpr (GLF) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) am[c] = T(ag[c]);
     }
 
     // Interface state: mean of the primitive variables of cells i and i+1.
@@ -404,7 +410,7 @@ __device__ __forceinline__ void store_face(T *__restrict__ flux, const FaceBox &
 template <int DIR, int FT>
 __host__ __device__ constexpr int tile_cells() { return DIR == 0 ? ROWS * NCX : TILE * (FT + 5); }
 
-template <int DIR, int FT, typename T, bool WZ = false>
+template <int DIR, int FT, typename T, bool WZ = false, bool GLF = false>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restrict__ flux,
                                            const Geom &G, const FaceBox &F, const Phys &P,
                                            int ta, int tb, T *sq)
@@ -437,7 +443,8 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
         pos[2] = F.lo[2] + row / F.cnt[1];
         if (row < nrows && pos[0] < F.cnt[0]) {
             T out[7];
-            face_flux<T, false, WZ>(sq, NC, w * NCX + lane, 1, P.gamma, P.igm1, (T)P.eps, out);
+            face_flux<T, false, WZ, GLF>(sq, NC, w * NCX + lane, 1, P.gamma, P.igm1, (T)P.eps, out, nullptr,
+                                         P.ag);
             store_face<N, T>(flux, F, pos, out);
         }
     } else {
@@ -462,7 +469,8 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
             pos[N] = f0 + ff;
             if (p < npos && pos[N] < F.cnt[N]) {
                 T out[7];
-                face_flux<T, false, WZ>(sq, NC, ff * TILE + lane, TILE, P.gamma, P.igm1, (T)P.eps, out);
+                face_flux<T, false, WZ, GLF>(sq, NC, ff * TILE + lane, TILE, P.gamma, P.igm1, (T)P.eps, out,
+                                             nullptr, P.ag);
                 store_face<N, T>(flux, F, pos, out);
             }
         }
@@ -605,7 +613,7 @@ __device__ __forceinline__ bool xseg_face(const FaceBox &F, const XSeg &X, int t
     return tid < X.nface;
 }
 
-template <typename T, bool WZ = false>
+template <typename T, bool WZ = false, bool GLF = false>
 __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__restrict__ flux,
                                                 const Geom &G, const FaceBox &F, const Phys &P,
                                                 long tile, T *sq)
@@ -616,7 +624,7 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
     int pos[3], off;
     if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T, false, WZ>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T, false, WZ, GLF>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out, nullptr, P.ag);
         store_face<0, T>(flux, F, pos, out);
     }
 }
@@ -666,7 +674,7 @@ __device__ __forceinline__ bool yz_face(const FaceBox &F, int ta, int tb, int ti
     return p < npos && pos[N] < F.cnt[N];
 }
 
-template <int DIR, int PW, typename T, bool WZ = false>
+template <int DIR, int PW, typename T, bool WZ = false, bool GLF = false>
 __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__restrict__ flux,
                                               const Geom &G, const FaceBox &F, const Phys &P,
                                               int ta, int tb, T *sq)
@@ -676,7 +684,8 @@ __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__rest
     int pos[3], off;
     if (yz_face<DIR, PW>(F, ta, tb, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T, false, WZ>(sq, yz_cells<PW>(), off, PW, P.gamma, P.igm1, (T)P.eps, out);
+        face_flux<T, false, WZ, GLF>(sq, yz_cells<PW>(), off, PW, P.gamma, P.igm1, (T)P.eps, out, nullptr,
+                                     P.ag);
         store_face<DIR, T>(flux, F, pos, out);
     }
 }

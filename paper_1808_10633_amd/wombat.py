@@ -24,11 +24,12 @@ WW_ERR_STATE = -7
 _NAMES = {0: "WW_OK", -1: "WW_ERR_INVALID_ARG", -2: "WW_ERR_UNSUPPORTED", -3: "WW_ERR_OOM",
           -4: "WW_ERR_HIP", -5: "WW_ERR_NONPHYSICAL", -6: "WW_ERR_USER_BC", -7: "WW_ERR_STATE"}
 
-ABI_VERSION = 3          # layout of Config below
+ABI_VERSION = 4          # layout of Config below
 WW_FP64 = 0
 WW_FP32_MIXED = 1
 WEIGHTS_JS, WEIGHTS_Z = 0, 1
 RK4, SSPRK3 = 0, 1
+LF_LOCAL, LF_GLOBAL = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_USER = 0, 1, 2
 
 USER_BC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p)
@@ -41,7 +42,7 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("bc", C.c_int * 6),
                 ("user_bc", USER_BC_FN), ("user_bc_ctx", C.c_void_p),
                 ("stream", C.c_void_p), ("device", C.c_int), ("weights", C.c_int),
-                ("integrator", C.c_int)]
+                ("integrator", C.c_int), ("lf_speed", C.c_int)]
 
 
 class WenoError(RuntimeError):
@@ -118,7 +119,8 @@ def last_error(ctx=None) -> str:
 
 def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, cfl=0.4,
                 eps=1e-6, precision=WW_FP64, bc=(0, 0, 0, 0, 0, 0), user_bc=None,
-                stream=None, device=0, weights=WEIGHTS_JS, integrator=RK4) -> Config:
+                stream=None, device=0, weights=WEIGHTS_JS, integrator=RK4,
+                lf_speed=LF_LOCAL) -> Config:
     cfg = Config()
     lib().wombat_weno_config_default(C.byref(cfg))
     cfg.nx, cfg.ny, cfg.nz, cfg.ng = nx, ny, nz, 3
@@ -134,6 +136,7 @@ def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, c
     cfg.device = device
     cfg.weights = weights
     cfg.integrator = integrator
+    cfg.lf_speed = lf_speed
     return cfg
 
 

@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wombat_weno_abi_version() == 3 == wombat.ABI_VERSION
+    assert lib.wombat_weno_abi_version() == 4 == wombat.ABI_VERSION
 
 
 def _cfg(**kw):
@@ -77,6 +77,7 @@ def test_default_config_is_valid(lib):
     (dict(weights=2), "weights"),
     (dict(weights=-1), "weights"),
     (dict(integrator=2), "integrator"),
+    (dict(lf_speed=3), "lf_speed"),
     (dict(bc=(0, 1, 0, 0, 0, 0)), "both faces"),
     (dict(bc=(2, 2, 0, 0, 0, 0)), "user_bc"),
     (dict(bc=(5, 5, 0, 0, 0, 0)), "unknown boundary"),
@@ -131,4 +132,16 @@ def test_integrator_default_and_batched_rejects_ssprk3(lib):
     h = C.c_void_p(1234)
     assert lib.wombat_weno_batch_init(C.byref(cfg), 1, dims, C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
     assert "RK4" in lib.wombat_weno_batch_last_error(None).decode()
+    assert h.value == 1234
+
+
+def test_lf_speed_default_and_batched_rejects_global(lib):
+    cfg = _cfg()
+    assert cfg.lf_speed == wombat.LF_LOCAL
+    cfg.lf_speed = wombat.LF_GLOBAL
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == 0
+    dims = (C.c_int32 * 3)(16, 16, 16)
+    h = C.c_void_p(1234)
+    assert lib.wombat_weno_batch_init(C.byref(cfg), 1, dims, C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
+    assert "LF" in lib.wombat_weno_batch_last_error(None).decode()
     assert h.value == 1234

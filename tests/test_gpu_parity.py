@@ -182,6 +182,61 @@ def test_wenoz_refused_by_batched_and_learned_forms():
         ctx.set_router(theta, 0.5)
 
 
+# global Lax-Friedrichs speeds (the LF-speed ablation): every tile kind
+GLF_CASES = ["turb_67x10x9", "turb_100x7x6", "smooth_13x70x11", "smooth_9x8x71", "xz_2d_outflow"]
+
+
+@pytest.mark.parametrize("case", GLF_CASES)
+def test_rhs_parity_global_lf(case):
+    say(f"[rhs parity, global LF speeds] {case}")
+    g, u = rhs_case(case)
+    ref_local = O.rhs(g, u)
+    g.lf_global = 1
+    ref = O.rhs(g, u)
+    ctx = ctx_for(g, lf_speed=W.LF_GLOBAL)
+    ug = to_gpu(u)
+    dg = torch.zeros_like(ug)
+    ctx.rhs(ug, dg)
+    torch.cuda.synchronize()
+    dxmin = min(d for d, n in ((g.dx, g.nx), (g.dy, g.ny), (g.dz, g.nz)) if n > 1)
+    err, _ = scaled_rhs_error(g.interior(dg.cpu().numpy()), g.interior(ref), g.interior(u), dxmin)
+    gap, _ = scaled_rhs_error(g.interior(ref_local), g.interior(ref), g.interior(u), dxmin)
+    say(f"  max scaled error {err:.3e} (local vs global in the oracle: {gap:.3e})")
+    assert err < TOL
+    assert gap > 1e3 * TOL
+
+
+def test_global_lf_brio_wu_10_steps_and_fp32():
+    say("[global LF] Brio-Wu 200 cells, 10 steps; 24^3 FP32 rhs")
+    g, u = rhs_case("brio_wu_1d")
+    g.lf_global = 1
+    ctx = ctx_for(g, lf_speed=W.LF_GLOBAL)
+    ug = to_gpu(u)
+    ref = u.copy()
+    for _ in range(10):
+        dto = O.cfl_dt(g, ref)
+        ctx.step(ug, dto)
+        O.rk4_step(g, ref, dto)
+    err, _ = scaled_state_error(g.interior(ug.cpu().numpy()), g.interior(ref))
+    say(f"  Brio-Wu scaled state error after 10 steps {err:.3e}")
+    assert err < TOL
+    n = 24
+    g3 = O.Grid(n, n, n, 1 / n, 1 / n, 1 / n, lf_global=1)
+    u3 = I.turbulence((n, n, n), mach=1.0, beta=100.0, seed=77, kmax=8).numpy().copy()
+    ref3 = O.rhs(g3, u3)
+    c32 = W.Context(n, n, n, precision=W.WW_FP32_MIXED, lf_speed=W.LF_GLOBAL)
+    ug3 = torch.from_numpy(u3).cuda().float()
+    dg3 = torch.zeros_like(ug3)
+    c32.rhs(ug3, dg3)
+    torch.cuda.synchronize()
+    e32, _ = scaled_rhs_error(g3.interior(dg3.double().cpu().numpy()), g3.interior(ref3), g3.interior(u3), 1 / n)
+    say(f"  fp32 rhs scaled error {e32:.3e}")
+    assert e32 < 2e-6
+    theta = torch.zeros(W.mlp_param_count(), dtype=torch.float32, device="cuda")
+    with pytest.raises(W.WenoError, match="LF"):
+        c32.set_router(theta, 0.5)
+
+
 # SSP-RK3 (the integrator ablation): steps against the oracle's textbook form
 @pytest.mark.parametrize("case,nsteps", [("brio_wu_1d", 10), ("turb_67x10x9", 5), ("smooth_13x70x11", 5)])
 def test_ssprk3_steps_parity(case, nsteps):
