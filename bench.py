@@ -32,12 +32,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
 # and ww_internal.h).
 MEASURED_TRAFFIC = {
-    ("48a95e5ba7fec6f5", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
+    ("5ed75ed674a8dca4", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("48a95e5ba7fec6f5", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
+    ("5ed75ed674a8dca4", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
-
 
 def sweep_source_hash():
     import hashlib
@@ -98,7 +97,7 @@ def roofline(ms, n, prec, fpi, peak):
             "frac": round(achieved / peak, 4),
             "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
             "traffic_source": tr["profile"] if tr else None,
-            "kernel": f"sweep_kernel<1,{'double' if prec == 'fp64' else 'float'}> (y sweep)",
+            "kernel": ("sweep_yz_kernel<1,32,double>" if prec == "fp64" else "sweep_kernel<1,8,float>") + " (y sweep)",
             "flop_per_interface": fpi, "interfaces_per_launch": nface,
             "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
                           "update": ms[4]}}

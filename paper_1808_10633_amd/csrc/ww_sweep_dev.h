@@ -60,12 +60,43 @@ __device__ __forceinline__ float frcp(float x)
     return fmaf(r, e, r);
 }
 
-// phi_N of eq. (2) with the weights of eqs. (3)-(7).  e4 = epsilon / 4.
+// Square roots of the scales 18 and 12 that fold the linear weights
+// d = (1, 6, 3)/10 and the 1/3, 1/6 of eq. (2) into the (epsilon + IS_k).
+constexpr double SQ18 = 4.2426406871192851464, SQ12 = 3.4641016151377545870;
+
+// phi_N of eq. (2) with the weights of eqs. (3)-(7).  ee = (epsilon/4,
+// sqrt(18) epsilon/4, sqrt(12) epsilon/4).
 // WZ: the WENO-Z weights of Borges et al. (2008) instead (exponent 1, an
 // ablation): alpha_k = d_k (1 + tau5 / (eps + IS_k)), tau5 = |IS_0 - IS_2|.
-template <typename T, bool LBL = false, bool WZ = false>
-__device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
+// LBL: also the largest deviation of a weight from the linear weights.
+// FOLD: the folded form below (fewer instructions; two more values live).
+template <typename T, bool LBL = false, bool WZ = false, bool FOLD = true>
+__device__ __forceinline__ T phi_n(T a, T b, T c, T d, const T (&ee)[3], T *dev = nullptr)
 {
+    if constexpr (!WZ && !LBL && FOLD) {
+        // With r_0 = sqrt(18) q_0, r_1 = q_1, r_2 = sqrt(12) q_2 (q_k as
+        // below) and R_k = r_k^2: A = R_1 R_2, B = R_0 R_1, C = R_0 R_2 are
+        // 12, 6 and 36 times the common-denominator numerators of alpha_0,
+        // alpha_2, alpha_1, so omega_0 = 3A / S and omega_2 = 6B / S with
+        // S = 3A + 6B + C, and eq. (2) becomes
+        //   phi = (A (a-2b+c) + B (b-2c+d)) / S - (b-2c+d)/12
+        // (one reciprocal, no separate scaling of the differences).
+        const T b2 = b * b, c2 = c * c;
+        T r0 = fma(a, fma(T(4 * SQ18), a, T(-11 * SQ18) * b), fma(T(10 * SQ18), b2, ee[1]));
+        T r1 = fma(T(4), b2 + c2, fma(T(-5), b * c, ee[0]));
+        T r2 = fma(d, fma(T(4 * SQ12), d, T(-11 * SQ12) * c), fma(T(10 * SQ12), c2, ee[2]));
+        if constexpr (sizeof(T) == 4) {
+            // FP32: keep the products of the squares in range (see below)
+            const T s = frcp(fmax(r0, fmax(r1, r2)));
+            r0 *= s; r1 *= s; r2 *= s;
+        }
+        r0 *= r0; r1 *= r1; r2 *= r2;
+        const T A = r1 * r2, B = r0 * r1;
+        const T inv = frcp(fma(T(3), A, fma(T(6), B, r0 * r2)));
+        const T y = fma(T(-2), c, b) + d;
+        return fma(fma(A, fma(T(-2), b, a) + c, B * y), inv, T(-1.0 / 12.0) * y);
+    }
+    const T e4 = ee[0];
     // Smoothness indicators of eqs. (5)-(7), expanded into the quadratic forms
     // IS_0 = 16a^2 - 44ab + 40b^2, IS_1 = 16b^2 - 20bc + 16c^2,
     // IS_2 = 40c^2 - 44cd + 16d^2 (all positive definite), and divided by 4
@@ -112,8 +143,8 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, T e4, T *dev = nullptr)
 // eq. (1) for one field.  cc: projected central term; df, du: projected flux
 // and state differences (k = 0..4 at i-3/2 .. i+5/2), both already carrying
 // the 1/2 of the Lax-Friedrichs split; al: LF speed.
-template <typename T, bool LBL = false, bool WZ = false>
-__device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, T eps,
+template <typename T, bool LBL = false, bool WZ = false, bool FOLD = true>
+__device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5], T al, const T (&ee)[3],
                                         T *dev = nullptr)
 {
     T dp[5], dm[5];
@@ -122,8 +153,8 @@ __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5]
         dp[k] = fma(al, du[k], df[k]);
         dm[k] = fma(-al, du[k], df[k]);
     }
-    return cc - phi_n<T, LBL, WZ>(dp[0], dp[1], dp[2], dp[3], eps, dev)
-              + phi_n<T, LBL, WZ>(dm[4], dm[3], dm[2], dm[1], eps, dev);
+    return cc - phi_n<T, LBL, WZ, FOLD>(dp[0], dp[1], dp[2], dp[3], ee, dev)
+              + phi_n<T, LBL, WZ, FOLD>(dm[4], dm[3], dm[2], dm[1], ee, dev);
 }
 
 // Stage one cell: sweep-frame conserved variables and derived quantities.
@@ -163,7 +194,8 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // from the linear weights (the label of a troubled interface).
 // GLF: the LF speed of field s is ag[s] (global speeds of the sweep, an
 // ablation) instead of the largest |lambda^s| over the six cells.
-template <typename T, bool LBL = false, bool WZ = false, bool GLF = false>
+// FOLD: phi_n's folded form (off where the register budget is exhausted).
+template <typename T, bool LBL = false, bool WZ = false, bool GLF = false, bool FOLD = true>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
                                           double gamma, double igm1, T eps, T (&out)[7],
                                           T *dev = nullptr, const double *ag = nullptr)
@@ -279,6 +311,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
 
     T G[7] = { T(0), T(0), T(0), T(0), T(0), T(0), T(0) };
     const T teps = T(0.25) * eps;     // epsilon / 4 for phi_n
+    const T ee[3] = { teps, teps * T(SQ18), teps * T(SQ12) };
 
     // One wave pair (sigma = -1 field index lo, sigma = +1 field index hi).
     // proj(X, odd, even) gives the odd and even parts of the row applied to X.
@@ -290,10 +323,10 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         T df[5], du[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] + odf[k]; du[k] = edu[k] + odu[k]; }
-        T fplus = weno_field<T, LBL, WZ>(ec + oc, df, du, am[hi], teps, dev);
+        T fplus = weno_field<T, LBL, WZ, FOLD>(ec + oc, df, du, am[hi], ee, dev);
 #pragma unroll
         for (int k = 0; k < 5; ++k) { df[k] = edf[k] - odf[k]; du[k] = edu[k] - odu[k]; }
-        T fminus = weno_field<T, LBL, WZ>(ec - oc, df, du, am[lo], teps, dev);
+        T fminus = weno_field<T, LBL, WZ, FOLD>(ec - oc, df, du, am[lo], ee, dev);
         S = fplus + fminus;
         D = fplus - fminus;
     };
@@ -327,7 +360,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
             df[k] = kh * (dY[k][0] - ke6 * dY[k][6]);
             du[k] = kh * (dZ[k][0] - ke6 * dZ[k][6]);
         }
-        G[0] += weno_field<T, LBL, WZ>(cc, df, du, am[3], teps, dev);
+        G[0] += weno_field<T, LBL, WZ, FOLD>(cc, df, du, am[3], ee, dev);
     }
 
     // back to (vt1, vt2), (Bt1, Bt2) and through dU/dW
@@ -624,7 +657,12 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
     int pos[3], off;
     if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        face_flux<T, false, WZ, GLF>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out, nullptr, P.ag);
+        // FP64 x segments: the folded phi_n needs the two scaled epsilons
+        // live across the fields, which pushes this kernel past 256 VGPRs
+        // (a scratch spill of ~2.7 GB of writes per 512^3 launch); the
+        // plain form fits and runs as fast
+        face_flux<T, false, WZ, GLF, (sizeof(T) == 4)>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out,
+                                                         nullptr, P.ag);
         store_face<0, T>(flux, F, pos, out);
     }
 }
