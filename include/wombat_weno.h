@@ -143,8 +143,10 @@ int wombat_weno_validate_config(const wombat_weno_config *cfg);
 int64_t wombat_weno_state_elems(const wombat_weno_config *cfg);
 
 /* Create a context: validates cfg, selects cfg->device and allocates every
- * device buffer the library will use (three state-sized work arrays, the face
- * fluxes of the three sweeps and small reduction buffers).  *out is written
+ * device buffer of the plain path (three state-sized work arrays, the face
+ * fluxes of the three sweeps, small reduction buffers and, with
+ * WW_LF_GLOBAL, 57 KB of LF-speed partials); wombat_weno_set_router
+ * allocates the learned form's buffers on its first call.  *out is written
  * only on success.  Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP. */
 int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out);
 
