@@ -32,9 +32,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
 # and ww_internal.h).
 MEASURED_TRAFFIC = {
-    ("5ed75ed674a8dca4", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
+    ("867c72de896930d2", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("5ed75ed674a8dca4", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
+    ("867c72de896930d2", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -158,20 +158,28 @@ def batched_form(a, wombat, inputs, opcount):
 
 
 def patch_sweep(a, wombat, inputs):
-    """Batched form at uniform patch edges 8..64, about 2^26 interior zones
+    """Batched form at uniform patch edges 4..72, about 2^26 interior zones
     each (the GPU counterpart of a patch-size study): every patch holds the
-    same periodic turbulence realisation (rms Mach 1, beta 100), FP32,
-    autotuned launch shape, graph-replayed steps."""
+    same periodic turbulence realisation (rms Mach 1, beta 100; modes up to
+    |k|/2pi = 8, or e/2 - 1 on patches under 8 cells), FP32, autotuned
+    launch shape, graph-replayed steps."""
     import tempfile
     import torch
     rows = []
-    for e in (8, 12, 16, 24, 32, 48, 64):
+    for e in (4, 6, 8, 12, 16, 24, 32, 48, 64, 72):
         npatch = max(1, (1 << 26) // e ** 3)
         bt = wombat.Batch([(e, e, e)] * npatch, 1.0 / e, precision=wombat.WW_FP32_MIXED)
         ar = bt.new_arena()
-        u = inputs.turbulence((e, e, e), mach=1.0, beta=100.0, seed=4000, dx=1.0 / e, device="cuda").float()
-        for p in range(npatch):
-            bt.view(ar, p).copy_(u)
+        # modes 2 <= |k|/2pi <= 8; patches under 8 cells keep |k|/2pi <= e/2 - 1
+        # (the generator's default band leaves them without a random field)
+        kmax = 8.0 if e >= 8 else e / 2 - 1
+        u = inputs.turbulence((e, e, e), mach=1.0, beta=100.0, seed=4000, dx=1.0 / e, kmin=min(2.0, kmax),
+                              kmax=kmax, device="cuda").float()
+        # equal patches sit at equal strides in the arena: one strided copy
+        stride = bt.offsets[1] - bt.offsets[0] if npatch > 1 else u.numel()
+        assert all(bt.offsets[p] == bt.offsets[0] + p * stride for p in range(npatch))
+        torch.as_strided(ar, (npatch, u.numel()), (stride, 1), bt.offsets[0]).copy_(
+            u.reshape(1, -1).expand(npatch, -1))
         torch.cuda.synchronize()
         cache = os.path.join(tempfile.mkdtemp(), "sweep_tune.jsonl")
         bt.autotune(ar, cache)

@@ -234,7 +234,7 @@ int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[
 typedef struct wombat_weno_batch wombat_weno_batch_t;
 
 /* Create a batch of npatch patches; dims (host) holds npatch x (nx, ny, nz),
- * each edge 8..1024 cells.  From cfg only dx (the cell width of every
+ * each edge 4..1024 cells (the 3-deep periodic ghosts need at least 3).  From cfg only dx (the cell width of every
  * patch and axis), gamma, cfl, eps, precision, stream and device are used.
  * Allocates three work arenas, the face-flux scratch of up to 4 blocks per
  * CU, the patch table and the patch order (largest first; in each stage the

@@ -196,7 +196,7 @@ hipError_t launch_ft(const BatchArgs<T> &a, int nblocks, hipStream_t st)
 
 }  // namespace
 
-bool batch_xflat_ok(int nx, long nrows) { return nx >= 8 && sw::xflat_cells(nx, nrows) <= sw::XF_MAXC; }
+bool batch_xflat_ok(int nx, long nrows) { return nx >= 4 && sw::xflat_cells(nx, nrows) <= sw::XF_MAXC; }
 
 template <typename T>
 hipError_t launch_batch_stage(const BatchArgs<T> &a, int ft, int nblocks, hipStream_t st)

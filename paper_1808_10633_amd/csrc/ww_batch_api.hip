@@ -278,8 +278,8 @@ int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int3
         return bfail(nullptr, WW_ERR_UNSUPPORTED, "the batched form uses the per-stencil LF speeds only");
     for (int p = 0; p < npatch; ++p)
         for (int d = 0; d < 3; ++d)
-            if (dims[3 * p + d] < 8 || dims[3 * p + d] > 1024)
-                return bfail(nullptr, WW_ERR_INVALID_ARG, "patch edges must be in 8..1024 cells");
+            if (dims[3 * p + d] < 4 || dims[3 * p + d] > 1024)
+                return bfail(nullptr, WW_ERR_INVALID_ARG, "patch edges must be in 4..1024 cells");
     wombat_weno_batch_t *b = new (std::nothrow) wombat_weno_batch();
     if (!b) return bfail(nullptr, WW_ERR_OOM, "host allocation failed");
     b->cfg = *cfg;

@@ -517,7 +517,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
 // rows touched hold at most xflat_cells(n, rows) cells; sq needs
 // NQ * XF_MAXC elements.
 constexpr int XF_FACES = TILE * ROWS;
-constexpr int XF_MAXC = 448;
+constexpr int XF_MAXC = 544;     // 4-cell rows: at most 53 rows of 10 cells
 __host__ __device__ inline int xflat_cells(int nx, long nrows)
 {
     long span = (XF_FACES + nx) / (nx + 1) + 1;

@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_helpers import say, scaled_state_error
+from gpu_helpers import random_smooth, say, scaled_state_error
 from oracle import oracle as O
 from paper_1808_10633_amd import inputs as I
 
@@ -60,6 +60,33 @@ def test_batch_step_equals_single_box_steps():
         worst = max(worst, err)
     say(f"  worst scaled difference batch vs single-box {worst:.3e}")
     assert worst < 1e-13
+
+
+@pytest.mark.parametrize("precision", [W.WW_FP64, W.WW_FP32_MIXED])
+def test_small_patches_equal_single_box_steps(precision):
+    # edges 4..7: flattened x rows of 4-7 cells (up to 53 rows per tile)
+    dims = [(4, 4, 4), (5, 6, 7), (6, 4, 9), (7, 7, 4), (4, 9, 5)]
+    say(f"[batch] small patches {dims}, precision {precision}")
+    bt = W.Batch(dims, DX, precision=precision)
+    ar = bt.new_arena()
+    for p, (nx, ny, nz) in enumerate(dims):
+        u = random_smooth(nx, ny, nz, seed=300 + p, amp=0.2)
+        bt.view(ar, p).copy_(torch.from_numpy(u).to(bt.view(ar, p).dtype))
+    before = [bt.view(ar, p).clone() for p in range(len(dims))]
+    bt.step(ar)
+    dts, flags = bt.dt()
+    assert (flags == 0).all()
+    worst = 0.0
+    for p, (nx, ny, nz) in enumerate(dims):
+        ctx = W.Context(nx, ny, nz, dx=DX, dy=DX, dz=DX, precision=precision)
+        u = before[p].clone()
+        ctx.step(u, float(dts[p]))
+        torch.cuda.synchronize()
+        sl = I.interior_slices(nx, ny, nz)
+        err, _ = scaled_state_error(bt.view(ar, p)[sl].double().cpu().numpy(), u[sl].double().cpu().numpy())
+        worst = max(worst, err)
+    say(f"  worst scaled difference batch vs single-box {worst:.3e}")
+    assert worst < (1e-13 if precision == W.WW_FP64 else 1e-6)
 
 
 def test_batch_against_oracle():
