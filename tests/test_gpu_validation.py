@@ -227,3 +227,53 @@ def test_kelvin_helmholtz_growth_at_the_paper_resolution():
         f"L1(rho) 64: {e[64]:.3e}, 128: {e[128]:.3e}")
     assert rel < 0.15
     assert e[64] > 2.0 * e[128]
+
+
+# Exact moving solutions (the closed forms of the oracle pins), on the GPU:
+# front within one cell of the exact position and parity with the oracle.
+def _moving_case(name):
+    import math
+    g53 = 5.0 / 3.0
+    if name == "contact":
+        WL = (2.0, 0.4, -0.3, 0.2, 0.7, 0.5, -0.4, 1.2)
+        WR = (0.5, 0.4, -0.3, 0.2, 0.7, 0.5, -0.4, 1.2)
+        return 200, WL, WR, g53, 0.3, 0.5, 0.3 + 0.4 * 0.5, lambda w: w[0]
+    if name == "rotational":
+        def st(a):
+            by, bz = 0.8 * math.cos(a), 0.8 * math.sin(a)
+            return (1.0, 0.2, -by, -bz, 1.0, by, bz, 1.0)
+        return 200, st(0.0), st(0.5 * math.pi), g53, 0.5, 0.1, 0.5 + 1.2 * 0.1, \
+            lambda w: np.unwrap(np.arctan2(w[6], w[5]))
+    # perpendicular fast shock, fast Mach 2 into gas at rest (compression from
+    # the Rankine-Hugoniot relations, bisection as in the oracle pin)
+    from test_oracle_moving import _perpendicular_shock
+    cf = math.sqrt(g53 + 1.0)
+    w = 2.0 * cf
+    r, p2 = _perpendicular_shock(1.0, 1.0, 1.0, w, g53)
+    WL = (r, w * (1 - 1 / r), 0.0, 0.0, 0.0, r, 0.0, p2)
+    WR = (1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 1.0)
+    return 400, WL, WR, g53, 0.25, 0.15, 0.25 + w * 0.15, lambda w_: w_[0]
+
+
+@pytest.mark.parametrize("name", ["contact", "rotational", "fast_shock"])
+def test_exact_moving_solutions_on_gpu(name):
+    from test_oracle_moving import _front
+    n, WL, WR, gamma, x0, T, x_exact, prof = _moving_case(name)
+    say(f"[moving] {name}: {n} cells to t = {T}")
+    u = I._tube(n, WL, WR, gamma, x0=x0)
+    g = O.Grid(n, dx=1.0 / n, gamma=gamma, bc=(1, 1, 0, 0, 0, 0))
+    ctx = W.Context(n, dx=1.0 / n, gamma=gamma, bc=(1, 1, 0, 0, 0, 0), precision=W.WW_FP64, cfl=0.4)
+    ug = torch.from_numpy(u.copy()).cuda()
+    ref = u.copy()
+    t = 0.0
+    while t < T - 1e-14:
+        dt = min(O.cfl_dt(g, ref), T - t)
+        O.rk4_step(g, ref, dt)
+        ctx.step(ug, dt)
+        t += dt
+    got = ug.cpu().numpy()
+    err, _ = scaled_state_error(g.interior(got), g.interior(ref))
+    xf = _front(prof(g.interior(got)[:, 0, 0]), n)
+    say(f"  front at {xf:.4f} (exact {x_exact:.4f}); scaled error vs oracle {err:.2e}")
+    assert abs(xf - x_exact) < 1.0 / n
+    assert err < 1e-11
