@@ -656,6 +656,7 @@ void orc_lf_global(const orc_grid *gr, const double *u, int d, double alpha[7])
         else { lo[e] = 0; hi[e] = 1; }
     }
     for (c = 0; c < 7; ++c) alpha[c] = 0.0;
+    if (!active(&G, d)) return;                     /* no sweep along an inactive axis */
     for (pos[2] = lo[2]; pos[2] < hi[2]; ++pos[2])
     for (pos[1] = lo[1]; pos[1] < hi[1]; ++pos[1])
     for (pos[0] = lo[0]; pos[0] < hi[0]; ++pos[0]) {

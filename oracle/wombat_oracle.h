@@ -53,7 +53,8 @@ void   orc_interface_flux_alpha(const double Us[48], double gamma, double eps, i
                                 const double alpha[7], double Fhat[8]);
 /* Global LF speeds of the d-sweep: per field, the largest |lambda^s| over
  * every cell a stencil of that sweep reads (the 3-deep ghosts along d, one
- * transverse ghost layer on active transverse axes). */
+ * transverse ghost layer on active transverse axes); zero on an inactive
+ * axis. */
 void   orc_lf_global(const orc_grid *g, const double *u, int d, double alpha[7]);
 double orc_weno_field_flux(const double f[6], const double u[6],
                            double alpha, double eps);
