@@ -271,14 +271,14 @@ int wombat_weno_batch_graph_steps(wombat_weno_batch_t *b, void *d_arena, int nst
  * of npatch entries, either may be NULL.  Synchronous. */
 int wombat_weno_batch_dt(wombat_weno_batch_t *b, double *h_dt, int32_t *h_flag);
 
-/* Launch shape in use: faces per y/z sweep tile (4 or 8), blocks per CU,
+/* Launch shape in use: faces per y/z sweep tile (4, 8, 12 or 16), blocks per CU,
  * total persistent blocks. */
 int wombat_weno_batch_shape(const wombat_weno_batch_t *b, int *ft, int *blocks_per_cu,
                             int *nblocks);
 
 /* Autotuner: if cache_path (a text file, one JSON object per line; may be
  * NULL) holds an entry for this patch set, precision and architecture, use
- * it; otherwise time one step of every launch shape (faces per tile 4 or 8 x
+ * it; otherwise time one step of every launch shape (faces per tile 4, 8, 12 or 16 x
  * 1..4 blocks per CU within the occupancy limit) on a private copy of
  * d_arena (not modified), keep the fastest, append it to cache_path, and
  * return its time in *best_ms (-1 when taken from the cache).  The copy is

@@ -201,7 +201,12 @@ bool batch_xflat_ok(int nx, long nrows) { return nx >= 4 && sw::xflat_cells(nx, 
 template <typename T>
 hipError_t launch_batch_stage(const BatchArgs<T> &a, int ft, int nblocks, hipStream_t st)
 {
-    return ft == 8 ? launch_ft<8, T>(a, nblocks, st) : launch_ft<4, T>(a, nblocks, st);
+    switch (ft) {
+    case 16: return launch_ft<16, T>(a, nblocks, st);
+    case 12: return launch_ft<12, T>(a, nblocks, st);
+    case 8: return launch_ft<8, T>(a, nblocks, st);
+    default: return launch_ft<4, T>(a, nblocks, st);
+    }
 }
 
 __global__ void batch_reset_kernel(int32_t *c, int n)
@@ -218,8 +223,12 @@ hipError_t launch_batch_reset(int32_t *counters, int n, hipStream_t st)
 template <typename T>
 hipError_t batch_occupancy(int ft, int *blocks_per_cu)
 {
-    return ft == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<8, T>, 256, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<4, T>, 256, 0);
+    switch (ft) {
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<16, T>, 256, 0);
+    case 12: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<12, T>, 256, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<8, T>, 256, 0);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<4, T>, 256, 0);
+    }
 }
 
 template hipError_t launch_batch_stage<double>(const BatchArgs<double> &, int, int, hipStream_t);

@@ -428,7 +428,8 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
     DevGuard dg(b->cfg.device);
     const std::string key = tune_key(b);
     int ft = 0, bpc = 0;
-    if (cache_lookup(cache_path, key, ft, bpc) && (ft == 4 || ft == 8) && bpc >= 1 && bpc <= 4) {
+    if (cache_lookup(cache_path, key, ft, bpc) && (ft == 4 || ft == 8 || ft == 12 || ft == 16) && bpc >= 1 &&
+        bpc <= 4) {
         if (best_ms) *best_ms = -1.0;
         return set_shape(b, ft, bpc);
     }
@@ -437,8 +438,8 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
     // device allocation, freed before it returns).
     double best = 1e300;
     int bft = 4, bb = 1;
-    const int fts[2] = { 4, 8 };
-    for (int fi = 0; fi < 2; ++fi)
+    const int fts[4] = { 4, 8, 12, 16 };
+    for (int fi = 0; fi < 4; ++fi)
         for (int c = 1; c <= 4; ++c) {
             rc = set_shape(b, fts[fi], c);
             if (rc) return rc;
