@@ -428,7 +428,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU path is a "
-              "design (halo-exchanged bricks), not part of this build", file=sys.stderr)
+              "design (halo-exchanged bricks) that the library does not implement", file=sys.stderr)
         sys.exit(2)
     if a.copy_mib:
         copy_calibration(a.copy_mib)

@@ -61,7 +61,7 @@ extern "C" {
 typedef enum {
     WW_OK = 0,
     WW_ERR_INVALID_ARG = -1,  /* bad pointer, size, alias or configuration   */
-    WW_ERR_UNSUPPORTED = -2,  /* valid request this build does not provide   */
+    WW_ERR_UNSUPPORTED = -2,  /* valid request the library does not provide */
     WW_ERR_OOM = -3,          /* device allocation failed in init            */
     WW_ERR_HIP = -4,          /* a HIP runtime call failed (sticky)          */
     WW_ERR_NONPHYSICAL = -5,  /* rho <= 0, p <= 0 or a non-finite value      */

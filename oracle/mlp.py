@@ -3,8 +3,7 @@
 TEST INFRASTRUCTURE ONLY: used by the tests and the benchmark's checks, never
 by the product path; shares no code with the HIP library.
 
-The router is the learned part of this build (it is not in the paper): an
-MLP 48 -> 32 -> 32 -> 1 with ReLU and a sigmoid output, trained with binary
+The router is not part of the paper's method: an MLP 48 -> 32 -> 32 -> 1 with ReLU and a sigmoid output, trained with binary
 cross-entropy on labels the full method produces:
 
   features: the six stencil cells i-2..i+3 of an interface, eight conserved

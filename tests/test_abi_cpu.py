@@ -27,7 +27,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(wombat.LIB_PATH):
-        pytest.fail("libwombat_weno.so is not built (run __graft_entry__.build())")
+        pytest.fail("libwombat_weno.so is not built (run paper_1808_10633_amd.build.build())")
     return wombat.lib()
 
 

@@ -289,7 +289,7 @@ def test_ssprk3_refused_by_stage_call_and_router():
 
 
 def test_alfven_wave_32cube_10_steps_every_step():
-    """The spec case: inclined Alfven wave, 32^3, CFL 0.4, 10 steps."""
+    """The inclined Alfven wave on a periodic 32^3 cube, CFL 0.4, 10 steps, checked every step."""
     n = 32
     say("[alfven 32^3] 10 steps")
     u, ca = I.alfven_wave_3d(n, amp=1e-6)
