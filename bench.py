@@ -88,6 +88,9 @@ def copy_calibration(mib):
     print(json.dumps({"copy_mib": mib, "bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+
+
 def roofline(ms, n, prec, fpi, peak):
     """Roofline of the dominant kernel (the y sweep) from event timings."""
     nface = (n + 1) * (n + 2) * (n + 2)
@@ -97,6 +100,9 @@ def roofline(ms, n, prec, fpi, peak):
             "frac": round(achieved / peak, 4),
             "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
             "traffic_source": tr["profile"] if tr else None,
+            # measured HBM bytes of the profiled launch over this run's launch time
+            "hbm_TBps": round((tr["read"] + tr["write"]) / (ms[2] * 1e-3) / 1e12, 3) if tr else None,
+            "hbm_frac": round((tr["read"] + tr["write"]) / (ms[2] * 1e-3) / HBM_PEAK, 4) if tr else None,
             "kernel": ("sweep_yz_kernel<1,32,double>" if prec == "fp64" else "sweep_kernel<1,8,float>") + " (y sweep)",
             "flop_per_interface": fpi, "interfaces_per_launch": nface,
             "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
