@@ -38,6 +38,27 @@ MEASURED_TRAFFIC = {
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
 
+# HBM bytes per stage launch of the batched kernel on the 4096-patch set
+# (autotuned faces per y/z tile -> read, write), from the same counter runs,
+# valid only for the batched source they were taken on (sha256 of
+# ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
+MEASURED_BATCH_TRAFFIC = {
+    ("661d5f031049d237", 4096, 4): (99.49e9, 39.44e9),
+    ("661d5f031049d237", 4096, 8): (90.40e9, 40.28e9),
+    ("661d5f031049d237", 4096, 12): (89.85e9, 40.62e9),
+    ("661d5f031049d237", 4096, 16): (88.47e9, 40.50e9),
+}
+BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
+
+
+def batch_source_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1808_10633_amd", "csrc")
+    src = b"".join(open(os.path.join(d, f), "rb").read()
+                   for f in ("ww_batch.hip", "ww_batch.h", "ww_sweep_dev.h", "ww_update_dev.h", "ww_internal.h"))
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
 def sweep_source_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_1808_10633_amd", "csrc")
@@ -148,6 +169,8 @@ def batched_form(a, wombat, inputs, opcount):
                 for x, y, z in dims)
     stage_ms = el / (4 * a.steps) * 1e3
     achieved = opcount.flops_per_interface() * faces / (stage_ms * 1e-3) / 1e12
+    tr = MEASURED_BATCH_TRAFFIC.get((batch_source_hash(), npatch, ft))
+    traffic = sum(tr) if tr else None
     res = {"value": zones * 4 * a.steps / el, "unit": "zone-stage updates/s",
            "ms_per_step": el / a.steps * 1e3, "dtype": "f32 (f64 islands)",
            "patches": npatch, "interior_zones": zones, "nonphysical_patches": int((flags > 0).sum()),
@@ -156,7 +179,11 @@ def batched_form(a, wombat, inputs, opcount):
                       "autotune_best_step_ms": tune_ms, "graph": True},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                        "traffic": None, "kernel": "batch_stage_kernel<FT,float> (whole stage)",
+                        "traffic": traffic, "traffic_unit": "bytes/launch",
+                        "traffic_source": BATCH_TRAFFIC_PROFILE if tr else None,
+                        "hbm_TBps": round(traffic / (stage_ms * 1e-3) / 1e12, 3) if tr else None,
+                        "hbm_frac": round(traffic / (stage_ms * 1e-3) / HBM_PEAK, 4) if tr else None,
+                        "kernel": "batch_stage_kernel<FT,float> (whole stage)",
                         "flop_per_interface": opcount.flops_per_interface(),
                         "interfaces_per_launch": faces, "kernel_ms": stage_ms}}
     del bt, ar
