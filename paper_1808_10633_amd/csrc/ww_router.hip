@@ -498,12 +498,14 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
     const int lane = threadIdx.x, w = threadIdx.y, tid = lane + 64 * w;
     int pos[3], off, cstr;
     bool act;
+    sw::stage_begin();
     if constexpr (DIR == 0) {
         cstr = 1;
         if (F.cnt[0] >= sw::XSEG_MIN) {
             const sw::XSeg X = sw::xseg_setup(F, blockIdx.x);
             sw::xseg_stage<float>(u, G, F, P, X, sq);
             __syncthreads();
+            sw::stage_end();
             act = sw::xseg_face(F, X, tid, pos, off);
         } else {
             const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
@@ -519,6 +521,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
                 }
             }
             __syncthreads();
+            sw::stage_end();
             const int row = ta * sw::ROWS + w;
             pos[0] = tb * sw::TILE + lane;
             pos[1] = F.lo[1] + row % F.cnt[1];
@@ -530,6 +533,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         cstr = YZ_PW;
         sw::yz_stage<DIR, YZ_PW, float>(u, G, F, P, blockIdx.x, blockIdx.y, sq);
         __syncthreads();
+        sw::stage_end();
         act = sw::yz_face<DIR, YZ_PW>(F, blockIdx.x, blockIdx.y, tid, pos, off);
     }
     // --- features and the MLP

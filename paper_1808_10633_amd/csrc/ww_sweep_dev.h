@@ -60,6 +60,15 @@ __device__ __forceinline__ float frcp(float x)
     return fmaf(r, e, r);
 }
 
+// Staging runs at a raised wave priority.  Two blocks share a CU, so while
+// one block stages its tile (global loads, equation of state, LDS writes) the
+// other is usually deep in its interface arithmetic; without the raise the
+// older waves of that block win the issue arbitration and the staging block's
+// loads and barrier are delayed.  The raise ends after the staging barrier.
+constexpr int STAGE_PRIO = 2;
+__device__ __forceinline__ void stage_begin() { __builtin_amdgcn_s_setprio(STAGE_PRIO); }
+__device__ __forceinline__ void stage_end() { __builtin_amdgcn_s_setprio(0); }
+
 // Square roots of the scales 18 and 12 that fold the linear weights
 // d = (1, 6, 3)/10 and the 1/3, 1/6 of eq. (2) into the (epsilon + IS_k).
 constexpr double SQ18 = 4.2426406871192851464, SQ12 = 3.4641016151377545870;
@@ -454,6 +463,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
     const int lane = threadIdx.x, w = threadIdx.y, tid = lane + TILE * w;
     const int nlast = G.n[N] + 2;   // last cell index along the sweep axis
 
+    stage_begin();
     if constexpr (DIR == 0) {
         const int nrows = F.cnt[1] * F.cnt[2];
         const int r0 = ta * ROWS;
@@ -469,6 +479,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
             }
         }
         __syncthreads();
+        stage_end();
         const int row = r0 + w;
         int pos[3];
         pos[0] = f0 + lane;
@@ -495,6 +506,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
             }
         }
         __syncthreads();
+        stage_end();
         for (int ff = w; ff < FT; ff += ROWS) {
             int pos[3];
             pos[A] = ca;
@@ -539,6 +551,7 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
     if (r_hi > nrows - 1) r_hi = nrows - 1;
     const int ncell = (int)(r_hi - r_lo + 1) * rowc;
     const int tid = threadIdx.x + TILE * threadIdx.y;
+    stage_begin();
     for (int c = tid; c < ncell; c += XF_FACES) {
         long row = r_lo + c / rowc;
         int x = c % rowc - 3;
@@ -547,6 +560,7 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
         stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XF_MAXC);
     }
     __syncthreads();
+    stage_end();
     const long g = g0 + tid;
     if (g < nrows * nf) {
         const long row = g / nf;
@@ -651,9 +665,11 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
                                                 const Geom &G, const FaceBox &F, const Phys &P,
                                                 long tile, T *sq)
 {
+    stage_begin();
     const XSeg X = xseg_setup(F, tile);
     xseg_stage<T>(u, G, F, P, X, sq);
     __syncthreads();
+    stage_end();
     int pos[3], off;
     if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
@@ -717,8 +733,10 @@ __device__ __forceinline__ void sweep_tile_yz(const T *__restrict__ u, T *__rest
                                               const Geom &G, const FaceBox &F, const Phys &P,
                                               int ta, int tb, T *sq)
 {
+    stage_begin();
     yz_stage<DIR, PW, T>(u, G, F, P, ta, tb, sq);
     __syncthreads();
+    stage_end();
     int pos[3], off;
     if (yz_face<DIR, PW>(F, ta, tb, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
