@@ -60,6 +60,37 @@ __device__ __forceinline__ float frcp(float x)
     return fmaf(r, e, r);
 }
 
+// Square root in FP64 for finite x >= 0: the hardware reciprocal-square-root
+// estimate, one Goldschmidt step towards g = sqrt(x), h = 1/(2 sqrt(x)), then
+// two Newton corrections g += (x - g^2) h with the residual formed by a fused
+// multiply-add (Markstein's formulation).  The estimate is taken at
+// x + 2^-1022, so x = 0 gives 0 and x < 0 gives NaN; the wave speeds and
+// normalisations passed here are never subnormal or infinite, so the range
+// scaling and special-case selects of the general routine are left out.
+__device__ __forceinline__ double fsqrt(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x + 0x1p-1022);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }
+
+// 1/sqrt(x) in FP64 for finite x > 0: the estimate refined by two Newton
+// steps y += y (1 - x y^2) / 2.
+__device__ __forceinline__ double frsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+
 // Staging runs at a raised wave priority.  Two blocks share a CU, so while
 // one block stages its tile (global loads, equation of state, LDS writes) the
 // other is usually deep in its interface arithmetic; without the raise the
@@ -185,15 +216,15 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
     T bt2 = (b1 * b1 + b2 * b2) * ir;
     T dd = a2 - bn2;
     T disc = dd * dd + bt2 * (T(2) * a2 + T(2) * bn2 + bt2);
-    T cf2 = T(0.5) * (a2 + bn2 + bt2 + sqrt(disc));
+    T cf2 = T(0.5) * (a2 + bn2 + bt2 + fsqrt(disc));
     T cs2 = a2 * bn2 * frcp(cf2);
     q[0 * qs] = r;  q[1 * qs] = mn; q[2 * qs] = m1; q[3 * qs] = m2;
     q[4 * qs] = bn; q[5 * qs] = b1; q[6 * qs] = b2; q[7 * qs] = e;
     q[8 * qs] = p;
     q[9 * qs] = ir;
-    q[10 * qs] = sqrt(cf2);
-    q[11 * qs] = sqrt(cs2);
-    q[12 * qs] = sqrt(bn2);
+    q[10 * qs] = fsqrt(cf2);
+    q[11 * qs] = fsqrt(cs2);
+    q[12 * qs] = fsqrt(bn2);
 }
 
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
@@ -258,7 +289,7 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     double bn2 = bnb * bnb * irb;
     double bt2 = (b1b * b1b + b2b * b2b) * irb;
     double dd = a2 - bn2;
-    double sqD = sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2));
+    double sqD = fsqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2));
     double cf2 = 0.5 * (a2 + bn2 + bt2 + sqD);
     double icf2 = frcp(cf2);
     double cs2 = a2 * bn2 * icf2;
@@ -273,11 +304,11 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         double isq = frcp(sqD);
         double af2 = fmin(fmax(a2 * P * icf2 * isq, 0.0), 1.0);
         double as2 = fmin(fmax(Q * isq, 0.0), 1.0);
-        af = sqrt(af2); as = sqrt(as2);
+        af = fsqrt(af2); as = fsqrt(as2);
     }
     double be1, be2;
     if (bt2 > 1e-24 * (a2 + bn2)) {
-        double ibt = frcp(sqrt(b1b * b1b + b2b * b2b));
+        double ibt = frsq(b1b * b1b + b2b * b2b);
         be1 = b1b * ibt; be2 = b2b * ibt;
     } else {
         // B_t ~ 0: any unit vector spans the degenerate wave pairs; the first
@@ -287,8 +318,8 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         be1 = 1.0; be2 = 0.0;
     }
     double sg = (bnb >= 0.0) ? 1.0 : -1.0;
-    double cfm = sqrt(cf2), csm = sqrt(cs2), am_ = sqrt(a2), sr = sqrt(rb);
-    double isr = frcp(sr), ia2 = frcp(a2);
+    double cfm = fsqrt(cf2), csm = fsqrt(cs2), am_ = fsqrt(a2);
+    double isr = frsq(rb), sr = rb * isr, ia2 = frcp(a2);
     double gm1 = gamma - 1.0;
     double hv2 = 0.5 * (vnb * vnb + v1b * v1b + v2b * v2b);
 
