@@ -32,9 +32,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
 # and ww_internal.h).
 MEASURED_TRAFFIC = {
-    ("ebccf4d2fc52ea57", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
+    ("d6932ea18544d211", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("ebccf4d2fc52ea57", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
+    ("d6932ea18544d211", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
                                         "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -43,10 +43,10 @@ MEASURED_TRAFFIC = {
 # valid only for the batched source they were taken on (sha256 of
 # ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
 MEASURED_BATCH_TRAFFIC = {
-    ("337c0fefe163dfe5", 4096, 4): (99.45e9, 39.51e9),
-    ("337c0fefe163dfe5", 4096, 8): (90.35e9, 40.30e9),
-    ("337c0fefe163dfe5", 4096, 12): (89.77e9, 40.65e9),
-    ("337c0fefe163dfe5", 4096, 16): (88.43e9, 40.50e9),
+    ("cf58697d1c9b416c", 4096, 4): (99.48e9, 39.50e9),
+    ("cf58697d1c9b416c", 4096, 8): (90.40e9, 40.29e9),
+    ("cf58697d1c9b416c", 4096, 12): (89.80e9, 40.63e9),
+    ("cf58697d1c9b416c", 4096, 16): (88.54e9, 40.49e9),
 }
 BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
 

@@ -5,10 +5,11 @@
 namespace ww {
 namespace {
 
-// At least two waves per SIMD.  The FP64 kernels sit at 252-253 VGPRs; without
-// this the WENO-Z instantiations take a few AGPRs more and drop to one wave
-// per SIMD (the x sweep ran 40 % slower); with it they spill 28-32 bytes per
-// lane to scratch instead.  The WENO-JS and FP32 code is unchanged by it.
+// At least two waves per SIMD.  The FP64 kernels sit at 248-253 VGPRs; without
+// this the WENO-Z instantiations took a few AGPRs more and dropped to one
+// wave per SIMD (the x sweep ran 40 % slower).  With it every sweep kernel
+// fits in 256 VGPRs without spilling.  The WENO-JS and FP32 code is unchanged
+// by it.
 #define WW_TWO_WAVES __attribute__((amdgpu_waves_per_eu(2)))
 
 template <int DIR, int FT, typename T, bool WZ, bool GLF>
