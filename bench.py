@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--batch-patches", type=int, default=4096,
                     help="patches of the batched form (0 skips it)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-router form")
+    ap.add_argument("--fp32-box", type=int, default=0,
+                    help="only the FP32 form on an N^3 box of the default turbulence (its own JSON line): "
+                         "sizes whose FP64 run does not fit one GPU")
     ap.add_argument("--patch-sweep", action="store_true",
                     help="only run the batched form at uniform patch sizes 8^3..64^3 (one JSON line)")
     ap.add_argument("--ablation", action="store_true",
@@ -187,6 +190,44 @@ def batched_form(a, wombat, inputs, opcount):
                         "flop_per_interface": opcount.flops_per_interface(),
                         "interfaces_per_launch": faces, "kernel_ms": stage_ms}}
     del bt, ar
+    return res
+
+
+def fp32_box(a, wombat, inputs, opcount):
+    """The FP32 form alone on an N^3 box of the default turbulence recipe (rms
+    Mach 1, beta 100, seed 1003), its own CFL dt every step: throughput,
+    event-timed kernels and the drift of the FP64 sums.  At 1024^3 the FP32
+    arrays (four states and three face-flux buffers, ~230 GB) fit one GPU; the
+    FP64 run at that size does not, so there is no FP64 comparison here."""
+    import torch
+    n = a.fp32_box
+    u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")
+    u32 = u.float().contiguous()
+    del u
+    torch.cuda.empty_cache()
+    print(f"[bench] {n}^3 FP32 turbulence ready", file=sys.stderr, flush=True)
+    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4)
+    s0 = ctx.sums(u32)
+    for _ in range(a.warmup):
+        ctx.step(u32, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ctx.step(u32, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = ctx.sums(u32)
+    ms = ctx.time_kernels(u32, reps=a.reps)
+    ifaces = (n + 1) * (n + 2) ** 2
+    achieved = opcount.flops_per_interface() * ifaces / (ms[2] * 1e-3) / 1e12
+    res = {"n": n, "value": n ** 3 * 4 * a.steps / el, "unit": "zone-stage updates/s",
+           "ms_per_step": el / a.steps * 1e3, "steps": a.steps, "warmup": a.warmup,
+           "dtype": "f32 (f64 islands)",
+           "kernel_ms": {k: v for k, v in zip(("ghosts", "sweep_x", "sweep_y", "sweep_z", "update"), ms)},
+           "y_sweep_tflops": round(achieved, 3), "y_sweep_frac_fp32_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+           "mass_energy_rel_drift": [abs(s1[v] - s0[v]) / abs(s0[v]) for v in (0, 7)],
+           "device_memory_gb": round(torch.cuda.mem_get_info()[1] / 1e9, 1)}
+    del ctx, u32
     return res
 
 
@@ -471,6 +512,9 @@ def main():
     from paper_1808_10633_amd import inputs, opcount, wombat
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.fp32_box:
+        print(json.dumps({"fp32_box": fp32_box(a, wombat, inputs, opcount)}), flush=True)
+        return
     if a.patch_sweep:
         print(json.dumps({"patch_sweep": patch_sweep(a, wombat, inputs), "unit": "zone-stage updates/s",
                           "dtype": "f32 (f64 islands)", "steps": a.steps}), flush=True)
