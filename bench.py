@@ -27,16 +27,12 @@ METRIC = "zone-stage updates/s (WENO5-MHD 512^3) FP64 vs FP32/learned at stated 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 
-# HBM bytes per launch of the timed sweep kernel from rocprofv3 FETCH_SIZE
-# and WRITE_SIZE runs (scaled by a 1 GiB copy; see profiles/), valid only for
-# the sweep source they were taken on (sha256 of ww_sweep.hip, ww_sweep_dev.h
-# and ww_internal.h).
-MEASURED_TRAFFIC = {
-    ("d6932ea18544d211", "fp64", 512): {"read": 20.48e9, "write": 8.07e9,
-                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("d6932ea18544d211", "fp32", 512): {"read": 10.48e9, "write": 4.16e9,
-                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (scaled
+# by a 1 GiB copy; see profiles/), valid only for the kernel source they were
+# taken on: sha256 of ww_sweep.hip + ww_sweep_dev.h (sweeps) or ww_update.hip
+# + ww_update_dev.h (update).
+MEASURED_TRAFFIC = {}
+MEASURED_UPDATE_TRAFFIC = {}
 
 # HBM bytes per stage launch of the batched kernel on the 4096-patch set
 # (autotuned faces per y/z tile -> read, write), from the same counter runs,
@@ -59,12 +55,19 @@ def batch_source_hash():
     return hashlib.sha256(src).hexdigest()[:16]
 
 
-def sweep_source_hash():
+def _source_hash(files):
     import hashlib
     d = os.path.join(ROOT, "paper_1808_10633_amd", "csrc")
-    src = b"".join(open(os.path.join(d, f), "rb").read()
-                   for f in ("ww_sweep.hip", "ww_sweep_dev.h", "ww_internal.h"))
+    src = b"".join(open(os.path.join(d, f), "rb").read() for f in files)
     return hashlib.sha256(src).hexdigest()[:16]
+
+
+def sweep_source_hash():
+    return _source_hash(("ww_sweep.hip", "ww_sweep_dev.h"))
+
+
+def update_source_hash():
+    return _source_hash(("ww_update.hip", "ww_update_dev.h"))
 
 
 def parse():
@@ -81,6 +84,10 @@ def parse():
     ap.add_argument("--fp32-box", type=int, default=0,
                     help="only the FP32 form on an N^3 box of the default turbulence (its own JSON line): "
                          "sizes whose FP64 run does not fit one GPU")
+    ap.add_argument("--precision-box", type=int, default=0,
+                    help="only the precision form against an FP64 run on an N^3 box (own JSON line), both "
+                         "in z-slab mode: 1024^3 FP64 fits one GPU that way")
+    ap.add_argument("--slab-planes", type=int, default=64, help="slab thickness of --precision-box")
     ap.add_argument("--patch-sweep", action="store_true",
                     help="only run the batched form at uniform patch sizes 8^3..64^3 (one JSON line)")
     ap.add_argument("--ablation", action="store_true",
@@ -93,7 +100,12 @@ def parse():
                     help="full-WENO FP32 steps that shock the learned-form turbulence")
     ap.add_argument("--learned-steps", type=int, default=50)
     ap.add_argument("--train-steps", type=int, default=3000)
-    ap.add_argument("--cpu-n", type=int, default=112)
+    ap.add_argument("--cpu-n", type=int, default=112, help="box of the single-core oracle sample")
+    ap.add_argument("--cpu-omp-n", type=int, default=192, help="box of the all-core oracle sample")
+    ap.add_argument("--compare-steps", type=int, default=50,
+                    help="steps after which the FP32 form is compared with the FP64 run")
+    ap.add_argument("--config2-steps", type=int, default=100,
+                    help="steps of the 256^3 subsonic FP64 turbulence form (0 skips it)")
     ap.add_argument("--reps", type=int, default=5, help="launches per kernel for the event timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
@@ -115,22 +127,63 @@ def copy_calibration(mib):
 HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
 
 
-def roofline(ms, n, prec, fpi, peak):
-    """Roofline of the dominant kernel (the y sweep) from event timings."""
+KERNELS = ("ghosts", "sweep_x", "sweep_y", "sweep_z", "update_stage", "cfl", "update_rhs")
+
+
+def kernel_table(ms, ms_per_step, stages=4):
+    """Event-timed kernels of a step and their sum against the step time."""
+    km = dict(zip(KERNELS, ms))
+    per_step = km["cfl"] + stages * sum(km[k] for k in ("ghosts", "sweep_x", "sweep_y", "sweep_z", "update_stage"))
+    return {"kernel_ms": km, "kernels_ms_per_step": round(per_step, 3),
+            "kernels_frac_of_step": round(per_step / ms_per_step, 4)}
+
+
+def roofline_sweep(ms_y, n, prec, opcount, peak):
+    """VALU roofline of the y sweep (the characteristic WENO flux of every
+    interface of one direction) from its event-timed launch."""
     nface = (n + 1) * (n + 2) * (n + 2)
-    achieved = fpi * nface / (ms[2] * 1e-3) / 1e12
+    fpi = opcount.flops_per_interface()
+    achieved = fpi * nface / (ms_y * 1e-3) / 1e12
+    dense = opcount.DENSE_FLOPS_PER_INTERFACE * nface / (ms_y * 1e-3) / 1e12
     tr = MEASURED_TRAFFIC.get((sweep_source_hash(), prec, n))
+    traffic = (tr["read"] + tr["write"]) if tr else None
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": (tr["read"] + tr["write"]) if tr else None, "traffic_unit": "bytes/launch",
+            "frac": round(achieved / peak, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
             "traffic_source": tr["profile"] if tr else None,
-            # measured HBM bytes of the profiled launch over this run's launch time
-            "hbm_TBps": round((tr["read"] + tr["write"]) / (ms[2] * 1e-3) / 1e12, 3) if tr else None,
-            "hbm_frac": round((tr["read"] + tr["write"]) / (ms[2] * 1e-3) / HBM_PEAK, 4) if tr else None,
+            "hbm_TBps": round(traffic / (ms_y * 1e-3) / 1e12, 3) if tr else None,
+            "hbm_frac": round(traffic / (ms_y * 1e-3) / HBM_PEAK, 4) if tr else None,
             "kernel": ("sweep_yz_kernel<1,32,double>" if prec == "fp64" else "sweep_kernel<1,8,float>") + " (y sweep)",
-            "flop_per_interface": fpi, "interfaces_per_launch": nface,
-            "kernel_ms": {"ghosts": ms[0], "sweep_x": ms[1], "sweep_y": ms[2], "sweep_z": ms[3],
-                          "update": ms[4]}}
+            "ms": ms_y, "flop_per_interface": fpi, "interfaces_per_launch": nface,
+            "frac_dense_count": round(dense / peak, 4),
+            "dense_flop_per_interface": opcount.DENSE_FLOPS_PER_INTERFACE}
+
+
+def roofline_update(ms_u, n, prec, opcount):
+    """HBM roofline of the flux-difference/CT/RK update in its stage forms:
+    algorithmic bytes per launch (face fluxes + RK arrays, averaged over the
+    four stage forms) over the event-timed launch."""
+    es = 8 if prec == "fp64" else 4
+    bpc = opcount.update_bytes_per_cell(es)
+    nbytes = bpc * n ** 3
+    achieved = nbytes / (ms_u * 1e-3) / 1e9
+    tr = MEASURED_UPDATE_TRAFFIC.get((update_source_hash(), prec, n))
+    traffic = (tr["read"] + tr["write"]) if tr else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+            "traffic_source": tr["profile"] if tr else None,
+            "kernel": f"update_march_kernel<{'double' if es == 8 else 'float'}> (RK stage forms)",
+            "ms": ms_u, "algorithmic_bytes_per_cell": bpc, "cells_per_launch": n ** 3}
+
+
+def rooflines(ms, n, prec, opcount, peak):
+    """Both rooflines; the dominant kernel is the one with the largest time
+    per step (each sweep direction and the update run once per stage)."""
+    sweep = roofline_sweep(ms[2], n, prec, opcount, peak)
+    upd = roofline_update(ms[4], n, prec, opcount)
+    longest = max(("sweep_x", ms[1]), ("sweep_y", ms[2]), ("sweep_z", ms[3]), ("update_stage", ms[4]),
+                  key=lambda t: t[1])[0]
+    dom = upd if longest == "update_stage" else sweep
+    return dict(dom, dominant=longest), {"sweep_y": sweep, "update": upd}
 
 
 def batched_form(a, wombat, inputs, opcount):
@@ -223,12 +276,86 @@ def fp32_box(a, wombat, inputs, opcount):
     res = {"n": n, "value": n ** 3 * 4 * a.steps / el, "unit": "zone-stage updates/s",
            "ms_per_step": el / a.steps * 1e3, "steps": a.steps, "warmup": a.warmup,
            "dtype": "f32 (f64 islands)",
-           "kernel_ms": {k: v for k, v in zip(("ghosts", "sweep_x", "sweep_y", "sweep_z", "update"), ms)},
+           "kernel_ms": dict(zip(KERNELS, ms)),
            "y_sweep_tflops": round(achieved, 3), "y_sweep_frac_fp32_peak": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
            "mass_energy_rel_drift": [abs(s1[v] - s0[v]) / abs(s0[v]) for v in (0, 7)],
            "device_memory_gb": round(torch.cuda.mem_get_info()[1] / 1e9, 1)}
     del ctx, u32
     return res
+
+
+def precision_box(a, wombat, inputs):
+    """The precision form against FP64 on an N^3 box of the default turbulence
+    recipe (rms Mach 1, beta 100, seed 1003): compare_steps FP64 steps with
+    their CFL dt, then the FP32 form replaying those dt from the same initial
+    state; L1 and Linf of every variable (relative to the FP64 field's mean
+    and largest magnitude) after the last step.  Both run in z-slab mode
+    (slab_planes): at 1024^3 the FP64 state, its stage state and accumulator
+    (3 x 69.9 GB) and one slab's face fluxes fit one GPU, where the whole-box
+    face fluxes would not."""
+    import torch
+    n = a.precision_box
+    nst = a.compare_steps
+
+    def ic():
+        u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003, device="cuda")
+        torch.cuda.empty_cache()
+        return u
+
+    def run(u, precision, dts, label):
+        ctx = wombat.Context(n, n, n, precision=precision, cfl=0.4, slab_planes=a.slab_planes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nst):
+            if dts is None:
+                dts_out.append(ctx.step(u, 0.0))
+            else:
+                ctx.cfl_dt(u)
+                ctx.step(u, dts[i])
+            if (i + 1) % 5 == 0:
+                torch.cuda.synchronize()
+                print(f"[bench] {label} step {i + 1}/{nst}, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ms = ctx.time_kernels(u, reps=2)
+        mem = torch.cuda.mem_get_info()
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        return {"value": n ** 3 * 4 * nst / el, "ms_per_step": el / nst * 1e3,
+                "kernel_ms_per_stage_all_slabs": dict(zip(KERNELS, ms)),
+                "device_memory_in_use_gb": round((mem[1] - mem[0]) / 1e9, 1)}
+
+    dts_out = []
+    u64 = ic()
+    print(f"[bench] {n}^3 FP64 initial state ready", file=sys.stderr, flush=True)
+    r64 = run(u64, wombat.WW_FP64, None, "fp64")
+    u32 = ic().float().contiguous()
+    torch.cuda.empty_cache()
+    r32 = run(u32, wombat.WW_FP32_MIXED, dts_out, "fp32")
+    l1, linf = [], []
+    g = 3
+    for v in range(8):
+        dsum = dmax = rsum = rmax = 0.0
+        for k0 in range(0, n, 64):
+            sl = (v, slice(g + k0, g + min(k0 + 64, n)), slice(g, g + n), slice(g, g + n))
+            ref = u64[sl]
+            d = (u32[sl].double() - ref).abs()
+            dsum += float(d.sum())
+            dmax = max(dmax, float(d.max()))
+            rsum += float(ref.abs().sum())
+            rmax = max(rmax, float(ref.abs().max()))
+        if rmax > 0:
+            l1.append(dsum / rsum)
+            linf.append(dmax / rmax)
+    return {"n": n, "steps": nst, "slab_planes": a.slab_planes, "fp64": r64, "fp32_mixed": r32,
+            "speedup_fp32_vs_fp64": r32["value"] / r64["value"],
+            "l1_rel_vs_fp64": l1, "linf_rel_vs_fp64": linf,
+            "l1_rel_vs_fp64_max_var": max(l1), "linf_rel_vs_fp64_max_var": max(linf),
+            "unit": "zone-stage updates/s",
+            "workload": f"decaying MHD turbulence {n}^3 periodic, rms Mach 1.0, beta 100, seed 1003; FP32 form "
+                        f"replays the FP64 run's CFL-0.4 steps"}
 
 
 def patch_sweep(a, wombat, inputs):
@@ -274,14 +401,15 @@ def patch_sweep(a, wombat, inputs):
     return rows
 
 
-def shocked_turbulence(n, seed, wombat, inputs, pre, snaps=()):
+def shocked_turbulence(n, seed, wombat, inputs, pre, snaps=(), learned=0):
     """Supersonic turbulence (rms Mach 3, beta 10, 10 % of the kinetic energy
     compressive, log-normal density sigma 0.5, p = 1), advanced `pre` full
     characteristic WENO FP32 steps at CFL 0.4.  Yields (step, context, state)
-    after each step listed in snaps and at the end."""
+    after each step listed in snaps and at the end; learned=1 gives the
+    context the router's buffers."""
     u = inputs.turbulence((n, n, n), mach=3.0, beta=10.0, seed=seed, compressive_fraction=0.1,
                           lognormal_sigma=0.5, device="cuda").float().contiguous()
-    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4)
+    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4, learned=learned)
     for s in range(1, pre + 1):
         ctx.step(u, 0.0)
         if s in snaps and s != pre:
@@ -345,7 +473,7 @@ def learned_form(a, wombat, inputs, router):
     del X, t, Xtr, ttr, Xva, tva
 
     n = a.learned_n
-    for _, ctx, u in shocked_turbulence(n, 5000, wombat, inputs, a.pre_steps):
+    for _, ctx, u in shocked_turbulence(n, 5000, wombat, inputs, a.pre_steps, learned=1):
         pass
     Xe, deve, exe, te = router.sample(ctx, u, 250000, seed=50000)
     ev = router.evaluate(theta, Xe, te, thr, excess=exe)
@@ -482,20 +610,95 @@ def ablation(a, wombat, inputs):
             "robustness": runs, "max_steps": a.abl_steps}
 
 
-def cpu_baseline(n):
-    """Serial FP64 oracle: one full RK4 step of the same turbulence recipe on
-    an n^3 box (a bounded sample of the 512^3 workload)."""
+def config2_form(a, wombat, inputs):
+    """Decaying subsonic MHD turbulence, 256^3 FP64 (rms Mach 0.5, beta 1e4,
+    seed 1002), advanced config2_steps CFL-0.4 steps from its initial state:
+    throughput and the invariants (sums of the conserved variables relative
+    to the sums of their absolute values; corner div B)."""
+    import torch
+    n = 256
+    u = inputs.turbulence((n, n, n), mach=0.5, beta=1e4, seed=1002, device="cuda")
+    ctx = wombat.Context(n, n, n, precision=wombat.WW_FP64, cfl=0.4)
+    sl = inputs.interior_slices(n, n, n)
+    s0 = ctx.sums(u)
+    scale = u[sl].abs().sum(dim=(1, 2, 3)).double().cpu().tolist()
+    d0, _ = ctx.divb(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.config2_steps):
+        ctx.step(u, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = ctx.sums(u)
+    d1, _ = ctx.divb(u)
+    drift = [abs(x - y) / z for x, y, z in zip(s1, s0, scale)]
+    res = {"value": n ** 3 * 4 * a.config2_steps / el, "unit": "zone-stage updates/s", "dtype": "f64",
+           "ms_per_step": el / a.config2_steps * 1e3, "steps": a.config2_steps,
+           "workload": "decaying MHD turbulence 256^3 periodic, rms Mach 0.5, beta 1e4, seed 1002, FP64, "
+                       "CFL 0.4 steps from the initial state (each step's CFL dt read back to the host)",
+           "sum_drift_rel_max": max(drift), "corner_divb_max": [d0, d1]}
+    print(f"[bench] 256^3 subsonic: {res['value']:.3e} zone-stage/s, sum drift {max(drift):.1e}, "
+          f"div B {d0:.1e} -> {d1:.1e}", file=sys.stderr, flush=True)
+    del ctx, u
+    return res
+
+
+def cpu_model():
+    """Host CPU model (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    """Threads the all-core oracle runs on: OMP_NUM_THREADS if set, else the
+    CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(n, n_omp):
+    """The FP64 oracle on the host: one full RK4 step (CFL dt + 4 stages) of
+    the same turbulence recipe, serial on an n^3 box and with OpenMP (the same
+    source, k-planes shared among threads) on all host threads on an n_omp^3
+    box: bounded samples of the 512^3 workload."""
     from oracle import oracle
     from paper_1808_10633_amd import inputs
-    u = inputs.turbulence((n, n, n), mach=1.0, beta=100.0, seed=1003).numpy().copy()
-    g = oracle.Grid(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n, cfl=0.4)
-    t0 = time.perf_counter()
-    dt = oracle.cfl_dt(g, u)
-    oracle.rk4_step(g, u, dt)
-    el = time.perf_counter() - t0
-    return {"value": n ** 3 * 4 / el, "unit": "zone-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RK4 step (4 stages) of the {n}^3 box of the same turbulence recipe, "
-                      f"serial C oracle, {el:.1f} s"}
+
+    def run(m, threads):
+        got = oracle.set_threads(threads)
+        u = inputs.turbulence((m, m, m), mach=1.0, beta=100.0, seed=1003).numpy().copy()
+        g = oracle.Grid(m, m, m, 1.0 / m, 1.0 / m, 1.0 / m, cfl=0.4)
+        t0 = time.perf_counter()
+        dt = oracle.cfl_dt(g, u)
+        oracle.rk4_step(g, u, dt)
+        return m ** 3 * 4 / (time.perf_counter() - t0), time.perf_counter() - t0, got
+
+    v1, t1, _ = run(n, 1)
+    threads = host_threads()
+    vn, tn, used = run(n_omp, threads)
+    oracle.set_threads(1)
+    model = cpu_model()
+    return {"value": vn, "unit": "zone-stage updates/s", "cores": used, "kind": "oracle",
+            "sample": f"one RK4 step (CFL dt + 4 stages) of the {n_omp}^3 box of the same turbulence recipe, "
+                      f"C oracle built with OpenMP over k-planes, {used} threads, {tn:.1f} s",
+            "cpu_model": model,
+            "single_core": {"value": v1, "cores": 1,
+                            "sample": f"one RK4 step of the {n}^3 box, serial C oracle, {t1:.1f} s"}}
 
 
 def main():
@@ -514,6 +717,9 @@ def main():
     torch.cuda.set_device(0)
     if a.fp32_box:
         print(json.dumps({"fp32_box": fp32_box(a, wombat, inputs, opcount)}), flush=True)
+        return
+    if a.precision_box:
+        print(json.dumps({"precision_box": precision_box(a, wombat, inputs)}), flush=True)
         return
     if a.patch_sweep:
         print(json.dumps({"patch_sweep": patch_sweep(a, wombat, inputs), "unit": "zone-stage updates/s",
@@ -538,25 +744,32 @@ def main():
     el = time.perf_counter() - t0
     print(f"[bench] {a.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
     zs = n ** 3 * 4 * a.steps / el
+    ms_step = el / a.steps * 1e3
 
-    # dominant kernel: the characteristic sweeps; HIP events on the library stream
+    # kernels of a step by HIP events on the library stream; the dominant one
+    # (longest per step) carries the roofline
     ms = ctx.time_kernels(u, reps=a.reps)
-    roof = roofline(ms, n, "fp64", opcount.flops_per_interface(), FP64_VECTOR_PEAK_TFLOPS)
+    roof, roofs = rooflines(ms, n, "fp64", opcount, FP64_VECTOR_PEAK_TFLOPS)
     out = {"metric": METRIC, "value": zs, "unit": "zone-stage updates/s", "n_gpus": 1,
-           "steps": a.steps, "warmup": a.warmup, "ms_per_step": el / a.steps * 1e3,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"decaying MHD turbulence {n}^3 periodic, rms Mach 1.0, beta 100, "
                                   "gamma 5/3, FP64 characteristic WENO5 + CT + RK4, CFL 0.4 step",
                       "n": n, "precision": "fp64"},
-           "roofline": roof}
+           "roofline": roof, "rooflines": roofs, "kernels": kernel_table(ms, ms_step)}
+    # the FP64 reference of the precision form continues, untimed, to the
+    # compared step count (the timed window is unchanged)
+    while len(dts) < a.compare_steps:
+        dts.append(ctx.step(u, 0.0))
+    torch.cuda.synchronize()
     del ctx
     torch.cuda.empty_cache()
 
     if not a.no_fp32:
         # precision form: FP32 state/fluxes/weights, FP64 islands; same initial
         # state, the FP64 run's step sizes replayed (its own CFL reduction
-        # still runs every step), final states compared
+        # still runs every step), final states compared after compare_steps
         u32 = u_ic.float().contiguous()
         c32 = wombat.Context(n, n, n, precision=wombat.WW_FP32_MIXED, cfl=0.4)
         for i in range(a.warmup):
@@ -569,6 +782,11 @@ def main():
             c32.step(u32, dts[a.warmup + i])
         torch.cuda.synchronize()
         el32 = time.perf_counter() - t0
+        ms32 = c32.time_kernels(u32, reps=a.reps)
+        for i in range(a.warmup + a.steps, len(dts)):
+            c32.cfl_dt(u32)
+            c32.step(u32, dts[i])
+        torch.cuda.synchronize()
         sl = inputs.interior_slices(n, n, n)
         l1, linf = [], []
         for v in range(8):
@@ -577,18 +795,24 @@ def main():
             if float(ref.max()) > 0:
                 l1.append(float(d.mean() / ref.mean()))
                 linf.append(float(d.max() / ref.max()))
-        ms32 = c32.time_kernels(u32, reps=a.reps)
+        r32, rs32 = rooflines(ms32, n, "fp32", opcount, FP32_VECTOR_PEAK_TFLOPS)
         out["forms"] = {"fp32_mixed": {
             "value": n ** 3 * 4 * a.steps / el32, "ms_per_step": el32 / a.steps * 1e3,
             "speedup_vs_fp64": (n ** 3 * 4 * a.steps / el32) / zs, "dtype": "f32 (f64 islands)",
             "l1_rel_vs_fp64_max_var": max(l1), "linf_rel_vs_fp64_max_var": max(linf),
-            "compared_after_steps": a.warmup + a.steps,
-            "roofline": roofline(ms32, n, "fp32", opcount.flops_per_interface(), FP32_VECTOR_PEAK_TFLOPS)}}
+            "l1_rel_vs_fp64": l1, "linf_rel_vs_fp64": linf,
+            "compared_after_steps": len(dts),
+            "roofline": r32, "rooflines": rs32, "kernels": kernel_table(ms32, el32 / a.steps * 1e3)}}
+        print(f"[bench] fp32 form: L1 {max(l1):.2e}, Linf {max(linf):.2e} after {len(dts)} steps",
+              file=sys.stderr, flush=True)
         del c32, u32
         torch.cuda.empty_cache()
     del u, u_ic
     torch.cuda.empty_cache()
 
+    if a.config2_steps > 0:
+        out.setdefault("forms", {})["fp64_256_subsonic"] = config2_form(a, wombat, inputs)
+        torch.cuda.empty_cache()
     if a.batch_patches > 0:
         out.setdefault("forms", {})["batched_fp32"] = batched_form(a, wombat, inputs, opcount)
         torch.cuda.empty_cache()
@@ -598,7 +822,7 @@ def main():
         torch.cuda.empty_cache()
     if not a.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(a.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.cpu_omp_n)
     print(json.dumps(out), flush=True)
 
 

@@ -44,8 +44,11 @@
  * several contexts may coexist.  All device work of a context is enqueued on
  * the stream given in the configuration (0 = the null stream), in call
  * order.  Calls documented as synchronous wait for that stream.  The library
- * allocates device memory only in wombat_weno_init and frees it only in
- * wombat_weno_destroy; it never frees caller memory.
+ * allocates device memory only in wombat_weno_init / wombat_weno_batch_init
+ * and frees it only in the matching destroy call; it never frees caller
+ * memory.  No other call allocates device or pinned host memory (stages,
+ * steps, routing, autotuning and graph replay included), so stages can be
+ * captured in HIP graphs; wombat_weno_alloc_count() lets a caller check this.
  */
 #ifndef WOMBAT_WENO_H
 #define WOMBAT_WENO_H
@@ -56,7 +59,7 @@
 extern "C" {
 #endif
 
-#define WOMBAT_WENO_ABI_VERSION 4
+#define WOMBAT_WENO_ABI_VERSION 5
 
 typedef enum {
     WW_OK = 0,
@@ -122,6 +125,18 @@ typedef struct {
                                 WW_RK4 only                                   */
     int lf_speed;            /* ww_lf_speed (added in ABI 4); the batched and
                                 learned forms accept WW_LF_LOCAL only          */
+    int learned;             /* 1: wombat_weno_init also allocates the learned
+                                router's buffers (see wombat_weno_set_router);
+                                FP32, WW_WEIGHTS_JS, WW_RK4 and WW_LF_LOCAL
+                                only; 0 (default): no routing (added in ABI 5) */
+    int slab_planes;         /* 0 (default): stages work on the whole box.
+                                >= 3: stages run in z-slabs of this many planes
+                                (needs nz >= 3; WW_RK4, WW_LF_LOCAL, no router):
+                                face fluxes are stored for one slab, not the
+                                box, wombat_weno_step keeps two work arrays
+                                instead of three, and wombat_weno_stage may
+                                write its output over its input (added in ABI 5).
+                                Results are identical bit for bit.           */
 } wombat_weno_config;
 
 typedef struct wombat_weno wombat_weno_t;
@@ -131,7 +146,7 @@ int wombat_weno_abi_version(void);
 
 /* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
  * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0,
- * WW_WEIGHTS_JS, WW_RK4, WW_LF_LOCAL.
+ * WW_WEIGHTS_JS, WW_RK4, WW_LF_LOCAL, learned 0, slab_planes 0.
  * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
 int wombat_weno_config_default(wombat_weno_config *cfg);
 
@@ -143,11 +158,17 @@ int wombat_weno_validate_config(const wombat_weno_config *cfg);
 int64_t wombat_weno_state_elems(const wombat_weno_config *cfg);
 
 /* Create a context: validates cfg, selects cfg->device and allocates every
- * device buffer of the plain path (three state-sized work arrays, the face
- * fluxes of the three sweeps, small reduction buffers and, with
- * WW_LF_GLOBAL, 57 KB of LF-speed partials); wombat_weno_set_router
- * allocates the learned form's buffers on its first call.  *out is written
- * only on success.  Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP. */
+ * device buffer the context will use: three state-sized work arrays (two
+ * with slab_planes), the face fluxes of the three sweeps (of one slab with
+ * slab_planes, plus a delay buffer of three planes), small reduction
+ * buffers, with
+ * WW_LF_GLOBAL 57 KB of LF-speed partials, and with cfg->learned the
+ * learned form's buffers (a state-sized backup, the packed parameters, a
+ * queue of one 8-byte entry per face of the largest sweep, one decision
+ * byte per face of every sweep).  *out is written only on success.
+ * Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP, WW_ERR_UNSUPPORTED
+ * (cfg->learned with a precision or scheme the router does not serve;
+ * slab_planes with WW_SSPRK3, WW_LF_GLOBAL or learned). */
 int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out);
 
 /* Release a context and its device memory.  NULL is allowed. */
@@ -187,9 +208,13 @@ int wombat_weno_rhs(wombat_weno_t *ctx, void *d_u, void *d_dudt);
  *   s=2: acc += dt/3 L(us),       out = u0 + dt   L(us)
  *   s=3:                          out = acc + dt/6 L(us)   (u0 unused)
  * Ghosts of d_us_in are filled first; interior cells of d_acc and d_us_out
- * are written.  d_us_out may alias d_u0 (pointwise), but not d_us_in or
- * d_acc.  dt must be finite and > 0.  Asynchronous.  WW_ERR_UNSUPPORTED on
- * a context configured with WW_SSPRK3. */
+ * are written.  d_us_out may alias d_u0 (pointwise), but not d_acc, nor
+ * d_us_in unless the context has slab_planes (then the stage writes over its
+ * input: the last three output planes of each slab wait in a delay buffer
+ * until the next slab has read its input, and the ghost cells of those
+ * planes are left zero; ghosts are refilled before every read).  dt must be
+ * finite and > 0.  Asynchronous.  WW_ERR_UNSUPPORTED on a context
+ * configured with WW_SSPRK3. */
 int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0,
                       void *d_us_in, void *d_acc, void *d_us_out);
 
@@ -211,13 +236,24 @@ int wombat_weno_sums(wombat_weno_t *ctx, const void *d_u, double out[8]);
 int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1);
 
 /* Kernel timing: average device time in milliseconds per launch of each
- * kernel of one right-hand-side evaluation of d_u, measured with HIP events
- * recorded on the context's stream around `reps` back-to-back launches
- * (reps in 1..1000): ms[0] the ghost fill of all axes, ms[1..3] the x, y and
- * z sweeps (0 for an inactive axis), ms[4] the flux-difference/CT/update
- * kernel (writing L(U) into a work array).  d_u's ghosts are filled.
- * Synchronous. */
-int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[5]);
+ * kernel of a step on the state d_u, measured with HIP events recorded on
+ * the context's stream around `reps` back-to-back launches after one untimed
+ * launch (reps in 1..1000): ms[0] the ghost fill of all axes, ms[1..3] the
+ * x, y and z sweeps (0 for an inactive axis), ms[4] the flux-difference/CT/
+ * update kernel in the stage forms a step runs (the mean over the four RK4
+ * stages, or the three SSP-RK3 stages, with u0 = d_u and the context's work
+ * arrays as accumulator and output, dt = 0), ms[5] the CFL reduction (both
+ * passes), ms[6] the update writing L(U) only (the form of wombat_weno_rhs).
+ * A step costs about ms[5] + stages * (ms[0] + ms[1] + ms[2] + ms[3] + ms[4]).
+ * With slab_planes, ms[1..4] and ms[6] are the launches of all slabs of a
+ * stage.
+ * d_u's ghosts are filled; the work arrays are overwritten.  Synchronous. */
+int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[7]);
+
+/* Device and pinned-host allocations the library has made since it was
+ * loaded (all contexts and batches of the process); a diagnostic that
+ * shows that calls after init allocate nothing. */
+int64_t wombat_weno_alloc_count(void);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent periodic patches (Sec. 2.2: the domain is
@@ -278,11 +314,14 @@ int wombat_weno_batch_shape(const wombat_weno_batch_t *b, int *ft, int *blocks_p
 
 /* Autotuner: if cache_path (a text file, one JSON object per line; may be
  * NULL) holds an entry for this patch set, precision and architecture, use
- * it; otherwise time one step of every launch shape (faces per tile 4, 8, 12 or 16 x
- * 1..4 blocks per CU within the occupancy limit) on a private copy of
- * d_arena (not modified), keep the fastest, append it to cache_path, and
- * return its time in *best_ms (-1 when taken from the cache).  The copy is
- * this set-up call's only device allocation.  Synchronous. */
+ * it; otherwise time every launch shape (faces per tile 4, 8, 12 or 16 x
+ * 1..4 blocks per CU within the occupancy limit) by the median of five
+ * launches of the second RK4 stage (its most expensive form), run on a copy
+ * of d_arena in the batch's own work arenas with zero RK weights (so the
+ * repeated launches do the same work), keep the fastest, append it to
+ * cache_path, and return its median stage time in *best_ms (-1 when taken
+ * from the cache).  d_arena is not modified; the call allocates nothing.  The per-patch time steps are recomputed from d_arena.
+ * Synchronous. */
 int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, const char *cache_path,
                                double *best_ms);
 
@@ -318,10 +357,10 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
  * take the linear flux in the routed sweep, troubled ones are queued and
  * take the full flux in a second pass; +1 sends every interface to the full
  * flux (the plain sweep) and -1 every one to the linear flux (the routed
- * sweep without evaluating the network).  The first call with a
- * non-NULL d_theta allocates one state-sized backup array, the packed
- * parameters, a queue of one 8-byte entry per face of the largest sweep and
- * one decision byte per face of every sweep (kept until destroy).
+ * sweep without evaluating the network).  A call with a non-NULL
+ * d_theta needs a context created with cfg.learned = 1, whose init
+ * allocated the buffers the router uses; it allocates nothing itself
+ * (WW_ERR_STATE on a context without them).
  * wombat_weno_step evaluates the network at its first stage and reuses
  * those decisions (one byte per face, kept in the context) for its other
  * three stages; wombat_weno_stage and wombat_weno_rhs evaluate it on every
@@ -329,8 +368,9 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
  * in the backup array, and if the routed step leaves a non-physical cell it
  * is redone from u^n with full characteristic WENO on every interface
  * (counted in router_stats).  Stages and rhs calls have no fallback.
- * WW_ERR_UNSUPPORTED on FP64 contexts, WW_ERR_INVALID_ARG for a threshold
- * or mode out of range, WW_ERR_OOM if the buffers cannot be allocated. */
+ * WW_ERR_UNSUPPORTED on FP64 contexts (and with WW_WEIGHTS_Z, WW_SSPRK3 or
+ * WW_LF_GLOBAL), WW_ERR_INVALID_ARG for a threshold or mode out of range,
+ * WW_ERR_STATE without cfg.learned. */
 int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double threshold, int mode);
 
 /* Interfaces routed to the linear flux by the three sweeps of the last

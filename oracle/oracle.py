@@ -21,18 +21,22 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wombat_oracle.c")
 _LIB = os.path.join(_HERE, "libwombat_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libwombat_oracle_omp.so")     # the same source with OpenMP
 
 # No fast-math and no FMA contraction: every operation rounds as written.
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc into ``oracle/libwombat_oracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, openmp: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/libwombat_oracle.so`` (with
+    openmp: the same source with -fopenmp into ``libwombat_oracle_omp.so``)."""
+    out = _LIB_OMP if openmp else _LIB
+    srcs = (_SRC, os.path.join(_HERE, "wombat_oracle.h"))
+    if force or not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(f) for f in srcs):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *(["-fopenmp"] if openmp else []), "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Grid(C.Structure):
@@ -83,53 +87,72 @@ class Grid:
 
 
 _lib = None
+_libs = {}
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def set_threads(n: int) -> int:
+    """Route the oracle's calls to the serial build (n == 1) or to the OpenMP
+    build of the same source with n host threads (n > 1).  Returns the
+    threads in use."""
+    global _lib
+    key = "omp" if n > 1 else "serial"
+    if key not in _libs:
+        _libs[key] = _load(build(openmp=(key == "omp")))
+    _lib = _libs[key]
+    return int(_lib.orc_set_threads(int(n)))
 
 
 def lib():
     global _lib
     if _lib is None:
-        L = C.CDLL(build())
-        d = C.c_double
-        L.orc_weno_weights.argtypes = [d, d, d, d, d, _dp, _dp]
-        L.orc_weno_phi.argtypes = [d, d, d, d, d]
-        L.orc_weno_weights_z.argtypes = [d, d, d, d, d, _dp, _dp]
-        L.orc_interface_flux_z.argtypes = [_dp, d, d, _dp]
-        L.orc_weno_phi.restype = d
-        L.orc_weno_field_flux.argtypes = [_dp, _dp, d, d]
-        L.orc_weno_field_flux.restype = d
-        L.orc_weno_field_flux_z.argtypes = [_dp, _dp, d, d]
-        L.orc_weno_field_flux_z.restype = d
-        L.orc_prim_to_cons.argtypes = [_dp, d, _dp]
-        L.orc_cons_to_prim.argtypes = [_dp, d, _dp]
-        L.orc_flux.argtypes = [_dp, C.c_int, d, _dp]
-        L.orc_wave_speeds.argtypes = [_dp, C.c_int, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
-        L.orc_eigensystem.argtypes = [_dp, d, _dp, _dp, _dp]
-        L.orc_interface_flux.argtypes = [_dp, d, d, _dp]
-        L.orc_interface_flux_ex.argtypes = [_dp, d, d, C.c_int, _dp, C.POINTER(d)]
-        L.orc_linear_flux.argtypes = [_dp, d, _dp]
-        g = C.POINTER(_Grid)
-        L.orc_state_size.argtypes = [g]
-        L.orc_state_size.restype = C.c_long
-        L.orc_fill_ghosts.argtypes = [g, _dp]
-        L.orc_rhs.argtypes = [g, _dp, _dp]
-        L.orc_rhs.restype = C.c_int
-        L.orc_rhs_nofill.argtypes = [g, _dp, _dp]
-        L.orc_rhs_nofill.restype = C.c_int
-        L.orc_rhs_linear.argtypes = [g, _dp, _dp]
-        L.orc_rhs_linear.restype = C.c_int
-        L.orc_cfl_dt.argtypes = [g, _dp]
-        L.orc_cfl_dt.restype = d
-        L.orc_rk4_step.argtypes = [g, _dp, d]
-        L.orc_rk4_step.restype = C.c_int
-        L.orc_ssprk3_step.argtypes = [g, _dp, d]
-        L.orc_ssprk3_step.restype = C.c_int
-        L.orc_lf_global.argtypes = [g, _dp, C.c_int, _dp]
-        L.orc_interface_flux_alpha.argtypes = [_dp, d, d, C.c_int, _dp, _dp]
-        L.orc_sums.argtypes = [g, _dp, _dp]
-        L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
-        _lib = L
+        _lib = _libs["serial"] = _load(build())
     return _lib
+
+
+def _load(path):
+    L = C.CDLL(path)
+    d = C.c_double
+    L.orc_weno_weights.argtypes = [d, d, d, d, d, _dp, _dp]
+    L.orc_weno_phi.argtypes = [d, d, d, d, d]
+    L.orc_weno_weights_z.argtypes = [d, d, d, d, d, _dp, _dp]
+    L.orc_interface_flux_z.argtypes = [_dp, d, d, _dp]
+    L.orc_weno_phi.restype = d
+    L.orc_weno_field_flux.argtypes = [_dp, _dp, d, d]
+    L.orc_weno_field_flux.restype = d
+    L.orc_weno_field_flux_z.argtypes = [_dp, _dp, d, d]
+    L.orc_weno_field_flux_z.restype = d
+    L.orc_prim_to_cons.argtypes = [_dp, d, _dp]
+    L.orc_cons_to_prim.argtypes = [_dp, d, _dp]
+    L.orc_flux.argtypes = [_dp, C.c_int, d, _dp]
+    L.orc_wave_speeds.argtypes = [_dp, C.c_int, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
+    L.orc_eigensystem.argtypes = [_dp, d, _dp, _dp, _dp]
+    L.orc_interface_flux.argtypes = [_dp, d, d, _dp]
+    L.orc_interface_flux_ex.argtypes = [_dp, d, d, C.c_int, _dp, C.POINTER(d)]
+    L.orc_linear_flux.argtypes = [_dp, d, _dp]
+    g = C.POINTER(_Grid)
+    L.orc_state_size.argtypes = [g]
+    L.orc_state_size.restype = C.c_long
+    L.orc_fill_ghosts.argtypes = [g, _dp]
+    L.orc_rhs.argtypes = [g, _dp, _dp]
+    L.orc_rhs.restype = C.c_int
+    L.orc_rhs_nofill.argtypes = [g, _dp, _dp]
+    L.orc_rhs_nofill.restype = C.c_int
+    L.orc_rhs_linear.argtypes = [g, _dp, _dp]
+    L.orc_rhs_linear.restype = C.c_int
+    L.orc_cfl_dt.argtypes = [g, _dp]
+    L.orc_cfl_dt.restype = d
+    L.orc_rk4_step.argtypes = [g, _dp, d]
+    L.orc_rk4_step.restype = C.c_int
+    L.orc_ssprk3_step.argtypes = [g, _dp, d]
+    L.orc_ssprk3_step.restype = C.c_int
+    L.orc_lf_global.argtypes = [g, _dp, C.c_int, _dp]
+    L.orc_interface_flux_alpha.argtypes = [_dp, d, d, C.c_int, _dp, _dp]
+    L.orc_sums.argtypes = [g, _dp, _dp]
+    L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
+    return L
 
 
 def _f64(a):

@@ -1,5 +1,9 @@
 /*
  * wombat_oracle.c -- serial FP64 CPU oracle for the WENO5 ideal-MHD stage.
+ * (Built a second time with OpenMP, the k-plane loops of the sweeps, the
+ * flux differences and the RK combinations run on several host threads; each
+ * value is computed by the same code either way, so both builds agree bit
+ * for bit.)
  *
  * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the CPU
  * baseline of the benchmark, never by the product path.  It shares no code
@@ -42,6 +46,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, BX = 4, BY = 5, BZ = 6, EN = 7 };
 
@@ -702,10 +709,15 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
         if (!active(&G, d)) continue;
         int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
         int perm[8] = { RHO, MX + d, MX + t1, MX + t2, BX + d, BX + t1, BX + t2, EN };
-        int pos[3];
+        int kk;
         double ag[7] = { 0, 0, 0, 0, 0, 0, 0 };
         if (gr->lf_global) orc_lf_global(gr, u, d, ag);
-        for (pos[2] = FF[d].lo[2]; pos[2] < FF[d].lo[2] + FF[d].cnt[2]; ++pos[2])
+        /* Interfaces are independent: with OpenMP the k-planes are shared
+         * among threads (each face is still computed by the same code). */
+#pragma omp parallel for schedule(static) reduction(|:bad)
+        for (kk = 0; kk < FF[d].cnt[2]; ++kk) {
+        int pos[3];
+        pos[2] = FF[d].lo[2] + kk;
         for (pos[1] = FF[d].lo[1]; pos[1] < FF[d].lo[1] + FF[d].cnt[1]; ++pos[1])
         for (pos[0] = FF[d].lo[0]; pos[0] < FF[d].lo[0] + FF[d].cnt[0]; ++pos[0]) {
             double Us[48], Fh[8];
@@ -724,11 +736,15 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
             long fi = fidx(&FF[d], pos[0], pos[1], pos[2]);
             for (c = 0; c < 8; ++c) FF[d].f[perm[c] * FF[d].total + fi] = Fh[c];
         }
+        }
     }
 
     /* Flux differences for rho, m, E (x, then y, then z) and CT for B. */
-    int pos[3];
-    for (pos[2] = 0; pos[2] < G.n[2]; ++pos[2])
+    int kc;
+#pragma omp parallel for schedule(static)
+    for (kc = 0; kc < G.n[2]; ++kc) {
+    int pos[3], dd;
+    pos[2] = kc;
     for (pos[1] = 0; pos[1] < G.n[1]; ++pos[1])
     for (pos[0] = 0; pos[0] < G.n[0]; ++pos[0]) {
         long id = cidx(&G, pos[0], pos[1], pos[2]);
@@ -736,14 +752,14 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
         int h;
         for (h = 0; h < 5; ++h) {
             double acc = 0.0;
-            for (d = 0; d < 3; ++d) {
-                if (!active(&G, d)) continue;
+            for (dd = 0; dd < 3; ++dd) {
+                if (!active(&G, dd)) continue;
                 int pp[3] = { pos[0], pos[1], pos[2] };
-                pp[d] = pos[d] + 1;
-                double fr = fget(&FF[d], hv[h], pp);
-                pp[d] = pos[d];
-                double fl = fget(&FF[d], hv[h], pp);
-                acc -= (fr - fl) / G.dl[d];
+                pp[dd] = pos[dd] + 1;
+                double fr = fget(&FF[dd], hv[h], pp);
+                pp[dd] = pos[dd];
+                double fl = fget(&FF[dd], hv[h], pp);
+                acc -= (fr - fl) / G.dl[dd];
             }
             dudt[hv[h] * G.sv + id] = acc;
         }
@@ -758,6 +774,7 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
                 val = face_bdot(&G, FF, n, 0, pos[a1], pos[a2]);
             dudt[(BX + n) * G.sv + id] = val;
         }
+    }
     }
 
     for (d = 0; d < 3; ++d) free(FF[d].f);
@@ -822,9 +839,12 @@ int orc_rk4_step(const orc_grid *gr, double *u, double dt)
     memcpy(tmp, u, sizeof(double) * n);
     for (s = 0; s < 4; ++s) {
         if (orc_rhs(gr, tmp, k[s]) != 0) bad = 1;
-        if (s < 3)
+        if (s < 3) {
+#pragma omp parallel for schedule(static)
             for (i = 0; i < n; ++i) tmp[i] = u[i] + a[s] * dt * k[s][i];
+        }
     }
+#pragma omp parallel for schedule(static)
     for (i = 0; i < n; ++i)
         u[i] = u[i] + dt / 6.0 * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
     orc_fill_ghosts(gr, u);
@@ -919,4 +939,17 @@ void orc_divb(const orc_grid *gr, const double *uin, double *max_abs, double *l1
     *max_abs = mx;
     *l1 = count ? sum / count : 0.0;
     free(u);
+}
+
+/* Threads of the OpenMP build (the k-plane loops above); the serial build
+ * ignores the pragmas and this call.  Returns the thread count in use. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -100,6 +100,7 @@ int    orc_rk4_step(const orc_grid *g, double *u, double dt);
  * Same contract as orc_rk4_step. */
 int    orc_ssprk3_step(const orc_grid *g, double *u, double dt);
 void   orc_sums(const orc_grid *g, const double *u, double out[8]);
+int    orc_set_threads(int n);      /* OpenMP build: threads in use (serial build: 1) */
 void   orc_divb(const orc_grid *g, const double *u, double *max_abs,
                 double *l1);
 

@@ -9,11 +9,50 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <string>
 
 using ww::FaceBox;
 using ww::Geom;
+using ww::dev_alloc;
+
+namespace ww {
+
+namespace {
+std::atomic<long long> g_allocs{ 0 };   // allocations since the library was loaded
+std::atomic<int> g_since_init{ 0 };     // allocations since the latest (batch) init
+}  // namespace
+
+static bool alloc_should_fail()
+{
+    const int k = ++g_since_init;
+    const char *f = getenv("WOMBAT_WENO_FAIL_ALLOC");
+    return f && atoi(f) == k;
+}
+
+hipError_t dev_alloc(void **p, size_t bytes)
+{
+    ++g_allocs;
+    if (alloc_should_fail()) { *p = nullptr; return hipErrorOutOfMemory; }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+hipError_t host_alloc(void **p, size_t bytes)
+{
+    ++g_allocs;
+    if (alloc_should_fail()) { *p = nullptr; return hipErrorOutOfMemory; }
+    hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) *p = nullptr;
+    return e;
+}
+
+void alloc_hook_reset() { g_since_init = 0; }
+long long alloc_total() { return g_allocs.load(); }
+
+}  // namespace ww
 
 struct wombat_weno {
     wombat_weno_config cfg;
@@ -43,6 +82,8 @@ struct wombat_weno {
     int router_reuse;      // stages 2-4 of a step: reuse the decisions of its first stage
     int64_t fallbacks;     // routed steps redone with full WENO
     double *lfg;           // global LF speeds: partials, then 7 per direction (WW_LF_GLOBAL only)
+    int slab;              // z-slab mode: planes per slab (0: whole box)
+    void *delay;           // slab mode: the last 3 output planes of a slab (8 vars x 3 planes)
     hipStream_t st;
     int sticky;            // a HIP error happened: every later call fails
     std::string err;
@@ -87,7 +128,13 @@ int hip_fail(wombat_weno_t *c, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
     } while (0)
 
-int validate(const wombat_weno_config *c, std::string &why)
+int validate(const wombat_weno_config *c, std::string &why) { return ww::validate_config(c, why); }
+
+}  // namespace
+
+void ww::set_global_error(const std::string &msg) { g_err = msg; }
+
+int ww::validate_config(const wombat_weno_config *c, std::string &why)
 {
     if (!c) { why = "config is NULL"; return WW_ERR_INVALID_ARG; }
     const int n[3] = { c->nx, c->ny, c->nz };
@@ -109,6 +156,12 @@ int validate(const wombat_weno_config *c, std::string &why)
     if (c->weights != WW_WEIGHTS_JS && c->weights != WW_WEIGHTS_Z) { why = "unknown weights"; return WW_ERR_INVALID_ARG; }
     if (c->integrator != WW_RK4 && c->integrator != WW_SSPRK3) { why = "unknown integrator"; return WW_ERR_INVALID_ARG; }
     if (c->lf_speed != WW_LF_LOCAL && c->lf_speed != WW_LF_GLOBAL) { why = "unknown lf_speed"; return WW_ERR_INVALID_ARG; }
+    if (c->learned != 0 && c->learned != 1) { why = "learned must be 0 or 1"; return WW_ERR_INVALID_ARG; }
+    if (c->slab_planes < 0 || (c->slab_planes > 0 && c->slab_planes < 3)) {
+        why = "slab_planes must be 0 or >= 3";
+        return WW_ERR_INVALID_ARG;
+    }
+    if (c->slab_planes > 0 && c->nz < 3) { why = "slab_planes needs an active z axis"; return WW_ERR_INVALID_ARG; }
     bool user = false;
     for (int f = 0; f < 6; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
@@ -124,6 +177,8 @@ int validate(const wombat_weno_config *c, std::string &why)
     return WW_OK;
 }
 
+namespace {
+
 long state_elems(const wombat_weno_config *c)
 {
     const int n[3] = { c->nx, c->ny, c->nz };
@@ -136,25 +191,25 @@ void make_geom(const wombat_weno_config *c, Geom &G, FaceBox F[3])
 {
     const int n[3] = { c->nx, c->ny, c->nz };
     const double dl[3] = { c->dx, c->dy, c->dz };
-    int N[3];
-    for (int d = 0; d < 3; ++d) {
-        G.n[d] = n[d];
-        G.act[d] = n[d] > 1;
-        G.g[d] = G.act[d] ? 3 : 0;
-        G.dl[d] = dl[d];
-        G.idl[d] = 1.0 / dl[d];
-        N[d] = n[d] + 2 * G.g[d];
-    }
-    G.s[0] = 1;
-    G.s[1] = N[0];
-    G.s[2] = (long)N[0] * N[1];
-    G.sv = (long)N[0] * N[1] * N[2];
-    G.base = G.g[0] + G.g[1] * G.s[1] + G.g[2] * G.s[2];
+    ww::box_geom(n, dl, G, F);
+}
+
+// Slab [k0, k0 + nk) of the box: the state geometry shifted by k0 planes
+// (cells 0..nk-1 of S are planes k0.. of the box, its ghost planes the box's
+// neighbouring planes) and the slab's face boxes in slab-local plane numbers:
+// x and y faces on planes -1..nk (constrained transport needs one plane
+// beyond the slab), z faces 0..nk.
+void slab_geom(const Geom &G, int k0, int nk, Geom &S, FaceBox F[3])
+{
+    S = G;
+    S.n[2] = nk;
+    S.base = G.base + (long)k0 * G.s[2];
     for (int d = 0; d < 3; ++d) {
         FaceBox &B = F[d];
         for (int e = 0; e < 3; ++e) {
-            if (e == d) { B.lo[e] = 0; B.cnt[e] = n[e] + 1; }
-            else if (G.act[e]) { B.lo[e] = -1; B.cnt[e] = n[e] + 2; }
+            const int n = e == 2 ? nk : G.n[e];
+            if (e == d) { B.lo[e] = 0; B.cnt[e] = n + 1; }
+            else if (G.act[e]) { B.lo[e] = -1; B.cnt[e] = n + 2; }
             else { B.lo[e] = 0; B.cnt[e] = 1; }
         }
         B.s[0] = 1;
@@ -164,15 +219,21 @@ void make_geom(const wombat_weno_config *c, Geom &G, FaceBox F[3])
     }
 }
 
-// Test hook: WOMBAT_WENO_FAIL_ALLOC=k makes the k-th device allocation of
-// init fail (1-based), to exercise the out-of-memory path.
-int g_alloc_count = 0;
-hipError_t dev_alloc(void **p, size_t bytes)
+// The learned form's buffers (cfg.learned): the routed-step backup, the
+// packed parameters, the troubled-interface queue and the decisions.
+bool alloc_router(wombat_weno_t *c)
 {
-    const char *f = getenv("WOMBAT_WENO_FAIL_ALLOC");
-    ++g_alloc_count;
-    if (f && atoi(f) == g_alloc_count) { *p = nullptr; return hipErrorOutOfMemory; }
-    return hipMalloc(p, bytes);
+    if (dev_alloc(&c->backup, c->elems * c->esize) != hipSuccess) return false;
+    if (dev_alloc((void **)&c->router_pk, ww::MLP_PACKED_BYTES) != hipSuccess) return false;
+    long most = 1, all = 1;
+    for (int d = 0; d < 3; ++d)
+        if (c->G.act[d]) {
+            most = std::max(most, ww::ROUTED_QUEUE_REGIONS * ww::routed_queue_capacity(d, c->F[d]));
+            all += c->F[d].sc;
+        }
+    return dev_alloc((void **)&c->queue, sizeof(unsigned long long) * most) == hipSuccess &&
+           dev_alloc((void **)&c->qcount, sizeof(int32_t) * ww::ROUTED_QUEUE_REGIONS) == hipSuccess &&
+           dev_alloc((void **)&c->rmask, all) == hipSuccess;
 }
 
 void release(wombat_weno_t *c)
@@ -190,6 +251,7 @@ void release(wombat_weno_t *c)
     if (c->rmask) (void)hipFree(c->rmask);
     if (c->qcount) (void)hipFree(c->qcount);
     if (c->lfg) (void)hipFree(c->lfg);
+    if (c->delay) (void)hipFree(c->delay);
     for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
@@ -220,11 +282,70 @@ int fill_ghosts_t(wombat_weno_t *c, T *u)
     return WW_OK;
 }
 
+// Slab mode (cfg.slab_planes): the stage in z-slabs of `slab` planes, so that
+// the face fluxes of one slab are stored instead of the whole box's, and the
+// stage may write its output over its input.  Slab j reads input planes
+// k0-3 .. k1+2 and writes output planes k0 .. k1-1; the next slab still reads
+// planes k1-3 .. k1-1, so with out == us those three output planes go to a
+// delay buffer and are copied over the input after the next slab's sweeps.
+// Each face flux and cell update is computed by the same kernels and code as
+// in the whole-box stage, so the results are identical bit for bit.
+template <typename T>
+int operator_slabs_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out, T *out,
+                     const ww::StageCoef &k)
+{
+    int rc = fill_ghosts_t<T>(c, us);
+    if (rc) return rc;
+    const ww::Geom &G = c->G;
+    const int nz = G.n[2], kz = c->slab;
+    const bool inplace = out == us;
+    ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
+    T *D = (T *)c->delay;
+    const long dsv = 3 * G.s[2];                          // variable stride of the delay buffer
+    const long dbase = G.g[0] * G.s[0] + G.g[1] * G.s[1];  // cell (0, 0, plane 0) in it
+    int pending = -1;                                     // first plane of D owed to us
+    for (int k0 = 0; k0 < nz; k0 += kz) {
+        const int k1 = std::min(k0 + kz, nz), nk = k1 - k0;
+        ww::Geom S;
+        ww::FaceBox F[3];
+        slab_geom(G, k0, nk, S, F);
+        for (int d = 0; d < 3; ++d)
+            if (G.act[d]) WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], S, F[d], P, c->cfg.weights, c->st));
+        if (pending >= 0) {
+            // the previous slab's last three planes: their input has been read
+            for (int v = 0; v < 8; ++v)
+                WW_CHECK(c, hipMemcpyAsync(us + v * G.sv + G.base - dbase + (long)pending * G.s[2], D + v * dsv,
+                                           sizeof(T) * dsv, hipMemcpyDeviceToDevice, c->st));
+            pending = -1;
+        }
+        const T *f0 = (const T *)c->ff[0], *f1 = (const T *)c->ff[1], *f2 = (const T *)c->ff[2];
+        if (inplace && k1 < nz) {
+            if (nk > 3) {
+                ww::Geom S1 = S;
+                S1.n[2] = nk - 3;
+                WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, f0, f1, f2, F, S1, k, c->st));
+            }
+            ww::Geom S2 = S;
+            S2.n[2] = 3;
+            S2.base = S.base + (long)(nk - 3) * G.s[2];
+            ww::FaceBox F2[3] = { F[0], F[1], F[2] };
+            for (int d = 0; d < 3; ++d) F2[d].lo[2] -= nk - 3;      // same faces, numbered from plane nk-3
+            WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, D, f0, f1, f2, F2, S2, k, c->st,
+                                             dbase - S2.base, dsv));
+            pending = k1 - 3;
+        } else {
+            WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, f0, f1, f2, F, S, k, c->st));
+        }
+    }
+    return WW_OK;
+}
+
 // Ghosts + sweeps + update (mode 0: out = L(U); mode 1: RK stage).
 template <typename T>
 int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out, T *out,
                const ww::StageCoef &k)
 {
+    if (c->slab) return operator_slabs_t<T>(c, us, u0, acc_in, acc_out, out, k);
     int rc = fill_ghosts_t<T>(c, us);
     if (rc) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
@@ -272,43 +393,105 @@ int cfl_device_t(wombat_weno_t *c, const T *u, double *d_dt, int32_t *d_flag)
     return WW_OK;
 }
 
+// Average device time of `reps` back-to-back launches of one kernel (after
+// one untimed launch), by HIP events on the context's stream.
+template <typename F>
+int time_launches(wombat_weno_t *c, int reps, F launch, double &ms)
+{
+    for (int r = 0; r <= reps; ++r) {
+        if (r == 1) WW_CHECK(c, hipEventRecord(c->ev[0], c->st));
+        int rc = launch();
+        if (rc) return rc;
+    }
+    WW_CHECK(c, hipEventRecord(c->ev[1], c->st));
+    WW_CHECK(c, hipEventSynchronize(c->ev[1]));
+    float t = 0.0f;
+    WW_CHECK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
+    ms = (double)t / reps;
+    return WW_OK;
+}
+
+// fn(S, F) for the whole box, or for each z-slab in slab mode; stops at the
+// first error.
+template <typename Fn>
+int for_slabs(wombat_weno_t *c, Fn fn)
+{
+    if (!c->slab) return fn(c->G, c->F);
+    for (int k0 = 0; k0 < c->G.n[2]; k0 += c->slab) {
+        ww::Geom S;
+        ww::FaceBox F[3];
+        slab_geom(c->G, k0, std::min(c->slab, c->G.n[2] - k0), S, F);
+        int rc = fn(S, F);
+        if (rc) return rc;
+    }
+    return WW_OK;
+}
+
 template <typename T>
-int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
+int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[7])
 {
     int rc = fill_ghosts_t<T>(c, u);
     if (rc) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
-    ww::StageCoef k{ 0, 0, 0.0, 0.0 };
     if (c->lfg)      // the global LF speeds, once, outside the timed launches
         for (int d = 0; d < 3; ++d)
             WW_CHECK(c, ww::launch_lf_global<T>(u, c->G, d, c->cfg.gamma, c->lfg,
                                                 c->lfg + ww::LF_PART_DOUBLES + 7 * d, c->st));
-    for (int which = 0; which < 5; ++which) {
-        ms[which] = 0.0;
-        if (which >= 1 && which <= 3 && !c->G.act[which - 1]) continue;
-        // one untimed launch, then `reps` timed ones
-        for (int r = 0; r <= reps; ++r) {
-            if (r == 1) WW_CHECK(c, hipEventRecord(c->ev[0], c->st));
-            if (which == 0) {
-                for (int ax = 0; ax < 3; ++ax)
-                    WW_CHECK(c, ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
-            } else if (which <= 3) {
-                int d = which - 1;
-                if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
-                WW_CHECK(c, ww::launch_sweep<T>(d, u, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
-            } else {
-                WW_CHECK(c, ww::launch_update<T>(nullptr, nullptr, nullptr, (T *)c->work[0],
-                                                 (const T *)c->ff[0], (const T *)c->ff[1],
-                                                 (const T *)c->ff[2], c->F, c->G, k, c->st));
-            }
-        }
-        WW_CHECK(c, hipEventRecord(c->ev[1], c->st));
-        WW_CHECK(c, hipEventSynchronize(c->ev[1]));
-        float t = 0.0f;
-        WW_CHECK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[1]));
-        ms[which] = (double)t / reps;
+    for (int i = 0; i < 7; ++i) ms[i] = 0.0;
+    auto chk = [&](hipError_t e) { return e == hipSuccess ? (int)WW_OK : hip_fail(c, e, "timed launch"); };
+    if ((rc = time_launches(c, reps, [&] {
+             for (int ax = 0; ax < 3; ++ax) {
+                 int r2 = chk(ww::launch_ghosts<T>(u, c->G, ax, c->cfg.bc, c->st));
+                 if (r2) return r2;
+             }
+             return (int)WW_OK;
+         }, ms[0])))
+        return rc;
+    for (int d = 0; d < 3; ++d) {
+        if (!c->G.act[d]) continue;
+        if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
+        if ((rc = time_launches(c, reps, [&] {
+                 return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
+                     return chk(ww::launch_sweep<T>(d, u, (T *)c->ff[d], S, F[d], P, c->cfg.weights, c->st));
+                 });
+             }, ms[1 + d])))
+            return rc;
     }
-    return WW_OK;
+    // the update in the forms a step runs: the four RK4 stages (or the three
+    // SSP-RK3 stages), u0 = u, acc and out in the work arrays, dt = 0 so that
+    // repeated launches leave acc and out unchanged; the mean of the forms
+    const T *fx = (const T *)c->ff[0], *fy = (const T *)c->ff[1], *fz = (const T *)c->ff[2];
+    T *acc = (T *)c->work[c->slab ? 1 : 2], *out = (T *)c->work[0];
+    const bool ssp = c->cfg.integrator == WW_SSPRK3;
+    const int nform = ssp ? 3 : 4;
+    double sum = 0.0;
+    for (int s = 0; s < nform; ++s) {
+        ww::StageCoef k = ssp ? ww::StageCoef{ 2, s, 0.0, 0.0, 1.0, s == 0 ? 0.0 : 0.5 }
+                              : ww::StageCoef{ 1, s, 0.0, 0.0 };
+        const T *acc_in = ssp ? (s == 0 ? nullptr : (const T *)c->work[1]) : (const T *)acc;
+        double t = 0.0;
+        if ((rc = time_launches(c, reps, [&] {
+                 return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
+                     return chk(ww::launch_update<T>(u, acc_in, acc, out, fx, fy, fz, F, S, k, c->st));
+                 });
+             }, t)))
+            return rc;
+        sum += t;
+    }
+    ms[4] = sum / nform;
+    // the CFL reduction of a step (both passes)
+    if ((rc = time_launches(c, reps, [&] {
+             return chk(ww::launch_cfl<T>(u, c->G, c->cfg.gamma, c->cfg.cfl, c->part, c->partflag, c->nblk,
+                                          c->dsmall, c->dflag, c->st));
+         }, ms[5])))
+        return rc;
+    // the update writing L(U) only (wombat_weno_rhs)
+    const ww::StageCoef k0{ 0, 0, 0.0, 0.0 };
+    return time_launches(c, reps, [&] {
+        return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
+            return chk(ww::launch_update<T>(nullptr, nullptr, nullptr, out, fx, fy, fz, F, S, k0, c->st));
+        });
+    }, ms[6]);
 }
 
 }  // namespace
@@ -316,6 +499,8 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[5])
 extern "C" {
 
 int wombat_weno_abi_version(void) { return WOMBAT_WENO_ABI_VERSION; }
+
+int64_t wombat_weno_alloc_count(void) { return (int64_t)ww::alloc_total(); }
 
 int wombat_weno_config_default(wombat_weno_config *cfg)
 {
@@ -352,9 +537,22 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
     if (!out) return fail_ctx(nullptr, WW_ERR_INVALID_ARG, "out is NULL");
     int rc = validate(cfg, why);
     if (rc) return fail_ctx(nullptr, rc, why);
+    if (cfg->learned) {
+        if (cfg->precision != WW_FP32_MIXED)
+            return fail_ctx(nullptr, WW_ERR_UNSUPPORTED, "the learned router runs on FP32 contexts");
+        if (cfg->weights != WW_WEIGHTS_JS || cfg->integrator != WW_RK4 || cfg->lf_speed != WW_LF_LOCAL)
+            return fail_ctx(nullptr, WW_ERR_UNSUPPORTED,
+                            "the learned router needs the WENO-JS weights, RK4 and per-stencil LF speeds");
+    }
+    if (cfg->slab_planes > 0) {
+        if (cfg->learned || cfg->integrator != WW_RK4 || cfg->lf_speed != WW_LF_LOCAL)
+            return fail_ctx(nullptr, WW_ERR_UNSUPPORTED,
+                            "slab_planes runs the RK4 stages with per-stencil LF speeds, without the router");
+    }
     wombat_weno_t *c = new (std::nothrow) wombat_weno();
     if (!c) return fail_ctx(nullptr, WW_ERR_OOM, "host allocation failed");
     c->cfg = *cfg;
+    c->slab = cfg->slab_planes > 0 ? std::min(cfg->slab_planes, cfg->nz) : 0;
     make_geom(cfg, c->G, c->F);
     c->esize = cfg->precision == WW_FP64 ? sizeof(double) : sizeof(float);
     c->elems = state_elems(cfg);
@@ -362,17 +560,33 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
     c->nblk = ww::cfl_blocks(c->G);
     DevGuard dg(cfg->device);
     if (!dg.ok) { delete c; return fail_ctx(nullptr, WW_ERR_HIP, "hipSetDevice failed"); }
-    g_alloc_count = 0;
+    ww::alloc_hook_reset();
     auto oom = [&](const char *what) {
         release(c);
         delete c;
         return fail_ctx(nullptr, WW_ERR_OOM, std::string("device allocation failed: ") + what);
     };
-    for (int i = 0; i < 3; ++i)
+    // slab mode: two work arrays (the stage state, updated in place, and the
+    // accumulator), face fluxes of one slab and the three-plane delay buffer
+    for (int i = 0; i < (c->slab ? 2 : 3); ++i)
         if (dev_alloc(&c->work[i], c->esize * c->elems) != hipSuccess) return oom("work arrays");
-    for (int d = 0; d < 3; ++d)
-        if (c->G.act[d] && dev_alloc(&c->ff[d], c->esize * ww::NFC * c->F[d].sc) != hipSuccess)
-            return oom("face fluxes");
+    {
+        ww::Geom S;
+        ww::FaceBox SF[3];
+        if (c->slab) slab_geom(c->G, 0, c->slab, S, SF);
+        for (int d = 0; d < 3; ++d)
+            if (c->G.act[d] && dev_alloc(&c->ff[d], c->esize * ww::NFC * (c->slab ? SF[d].sc : c->F[d].sc)) != hipSuccess)
+                return oom("face fluxes");
+    }
+    if (c->slab) {
+        const size_t db = c->esize * 8 * 3 * c->G.s[2];
+        if (dev_alloc(&c->delay, db) != hipSuccess) return oom("slab delay buffer");
+        if (hipMemset(c->delay, 0, db) != hipSuccess) {
+            release(c);
+            delete c;
+            return fail_ctx(nullptr, WW_ERR_HIP, "hipMemset of the delay buffer failed");
+        }
+    }
     if (dev_alloc((void **)&c->part, sizeof(double) * 8 * c->nblk) != hipSuccess) return oom("partials");
     if (dev_alloc((void **)&c->partflag, sizeof(int32_t) * c->nblk) != hipSuccess) return oom("flags");
     if (dev_alloc((void **)&c->dsmall, sizeof(double) * 20) != hipSuccess) return oom("results");
@@ -380,10 +594,7 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
         dev_alloc((void **)&c->lfg, sizeof(double) * (ww::LF_PART_DOUBLES + 21)) != hipSuccess)
         return oom("global LF speeds");
     c->dflag = (int32_t *)(c->dsmall + 16);
-    if (hipHostMalloc((void **)&c->hsmall, sizeof(double) * 20, hipHostMallocDefault) != hipSuccess) {
-        c->hsmall = nullptr;
-        return oom("pinned host buffer");
-    }
+    if (ww::host_alloc((void **)&c->hsmall, sizeof(double) * 20) != hipSuccess) return oom("pinned host buffer");
     if (cfg->precision == WW_FP32_MIXED) {
         long tot = 0;
         for (int d = 0; d < 3; ++d) {
@@ -392,6 +603,7 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
         }
         if (dev_alloc((void **)&c->nsmooth, sizeof(int32_t) * (tot > 0 ? tot : 1)) != hipSuccess)
             return oom("router counters");
+        if (cfg->learned && !alloc_router(c)) return oom("learned-form buffers");
     }
     for (int i = 0; i < 2; ++i)
         if (hipEventCreate(&c->ev[i]) != hipSuccess) {
@@ -502,7 +714,8 @@ int wombat_weno_stage(wombat_weno_t *ctx, int s, double dt, const void *d_u0, vo
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "dt must be finite and > 0");
     if (!d_us_in || !d_acc || !d_us_out || (s < 3 && !d_u0))
         return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
-    if (d_us_out == d_us_in) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_us_out must not alias d_us_in");
+    if (d_us_out == d_us_in && !ctx->slab)
+        return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_us_out must not alias d_us_in (except with slab_planes)");
     if (d_acc == d_us_in || d_acc == d_us_out || (s < 3 && d_acc == d_u0))
         return fail_ctx(ctx, WW_ERR_INVALID_ARG, "d_acc must not alias the other arrays");
     DevGuard dg(ctx->cfg.device);
@@ -522,8 +735,17 @@ namespace {
 // the first stage and its decisions reused for the other three.
 int rk4_stages(wombat_weno_t *ctx, void *d_u, double dt)
 {
-    void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
     int rc;
+    if (ctx->slab) {
+        // the stage state A is updated in place; acc accumulates
+        void *A = ctx->work[0], *acc = ctx->work[1];
+        if (!(rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A)) &&
+            !(rc = wombat_weno_stage(ctx, 1, dt, d_u, A, acc, A)) &&
+            !(rc = wombat_weno_stage(ctx, 2, dt, d_u, A, acc, A)))
+            rc = wombat_weno_stage(ctx, 3, dt, d_u, A, acc, d_u);
+        return rc;
+    }
+    void *A = ctx->work[0], *B = ctx->work[1], *acc = ctx->work[2];
     ctx->router_reuse = 0;
     if ((rc = wombat_weno_stage(ctx, 0, dt, d_u, d_u, acc, A))) return rc;
     ctx->router_reuse = ctx->router ? 1 : 0;
@@ -642,7 +864,7 @@ int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1)
     return WW_OK;
 }
 
-int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[5])
+int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[7])
 {
     int rc = precheck(ctx);
     if (rc) return rc;
@@ -668,40 +890,10 @@ int wombat_weno_set_router(wombat_weno_t *ctx, const float *d_theta, double thre
     if (!d_theta) { ctx->router = 0; return WW_OK; }
     if (!(threshold > 0.0 && threshold < 1.0)) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "threshold must be in (0, 1)");
     if (mode < -1 || mode > 1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "mode must be -1, 0 or 1");
+    if (!ctx->router_pk)
+        return fail_ctx(ctx, WW_ERR_STATE, "the context was created without cfg.learned = 1 (the learned "
+                                           "form's buffers are allocated by wombat_weno_init)");
     DevGuard dg(ctx->cfg.device);
-    if (!ctx->backup) {
-        if (dev_alloc(&ctx->backup, ctx->elems * ctx->esize) != hipSuccess) {
-            ctx->backup = nullptr;
-            (void)hipGetLastError();
-            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the routed-step backup");
-        }
-    }
-    if (!ctx->router_pk) {
-        if (dev_alloc((void **)&ctx->router_pk, ww::MLP_PACKED_BYTES) != hipSuccess) {
-            ctx->router_pk = nullptr;
-            (void)hipGetLastError();
-            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the router parameters");
-        }
-    }
-    if (!ctx->queue) {
-        long most = 1, all = 1;
-        for (int d = 0; d < 3; ++d)
-            if (ctx->G.act[d]) {
-                most = std::max(most, ww::ROUTED_QUEUE_REGIONS * ww::routed_queue_capacity(d, ctx->F[d]));
-                all += ctx->F[d].sc;
-            }
-        if (dev_alloc((void **)&ctx->queue, sizeof(unsigned long long) * most) != hipSuccess ||
-            dev_alloc((void **)&ctx->qcount, sizeof(int32_t) * ww::ROUTED_QUEUE_REGIONS) != hipSuccess ||
-            dev_alloc((void **)&ctx->rmask, all) != hipSuccess) {
-            if (ctx->queue) (void)hipFree(ctx->queue);
-            if (ctx->qcount) (void)hipFree(ctx->qcount);
-            ctx->queue = nullptr;
-            ctx->qcount = nullptr;
-            ctx->rmask = nullptr;
-            (void)hipGetLastError();
-            return fail_ctx(ctx, WW_ERR_OOM, "no device memory for the troubled-interface queue");
-        }
-    }
     WW_CHECK(ctx, ww::launch_pack_mlp(d_theta, ctx->router_pk, ctx->st));
     ctx->router = 1;
     ctx->router_thr = (float)std::log(threshold / (1.0 - threshold));

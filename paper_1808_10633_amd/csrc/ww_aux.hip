@@ -282,6 +282,36 @@ __global__ __launch_bounds__(RB) void divb_final(const double *part, int nblk, d
 
 }  // namespace
 
+void box_geom(const int n[3], const double dl[3], Geom &G, FaceBox F[3])
+{
+    int N[3];
+    for (int d = 0; d < 3; ++d) {
+        G.n[d] = n[d];
+        G.act[d] = n[d] > 1;
+        G.g[d] = G.act[d] ? 3 : 0;
+        G.dl[d] = dl[d];
+        G.idl[d] = 1.0 / dl[d];
+        N[d] = n[d] + 2 * G.g[d];
+    }
+    G.s[0] = 1;
+    G.s[1] = N[0];
+    G.s[2] = (long)N[0] * N[1];
+    G.sv = (long)N[0] * N[1] * N[2];
+    G.base = G.g[0] + G.g[1] * G.s[1] + G.g[2] * G.s[2];
+    for (int d = 0; d < 3; ++d) {
+        FaceBox &B = F[d];
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) { B.lo[e] = 0; B.cnt[e] = n[e] + 1; }
+            else if (G.act[e]) { B.lo[e] = -1; B.cnt[e] = n[e] + 2; }
+            else { B.lo[e] = 0; B.cnt[e] = 1; }
+        }
+        B.s[0] = 1;
+        B.s[1] = B.cnt[0];
+        B.s[2] = (long)B.cnt[0] * B.cnt[1];
+        B.sc = (long)B.cnt[0] * B.cnt[1] * B.cnt[2];
+    }
+}
+
 int cfl_blocks(const Geom &G)
 {
     long ncell = (long)G.n[0] * G.n[1] * G.n[2];

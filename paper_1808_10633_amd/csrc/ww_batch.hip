@@ -167,6 +167,8 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
         ua.ff[0] = fx; ua.ff[1] = fy; ua.ff[2] = fz;
         ua.fb[0] = D.F[0]; ua.fb[1] = D.F[1]; ua.fb[2] = D.F[2];
         ua.G = G;
+        ua.odelta = 0;
+        ua.osv = G.sv;
         ua.c.mode = 1;
         ua.c.s = a.s;
         ua.c.bdt = a.bw * dtp;

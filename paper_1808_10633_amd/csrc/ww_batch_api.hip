@@ -160,6 +160,30 @@ int set_shape(wombat_weno_batch_t *b, int ft, int bpc)
 }
 
 template <typename T>
+BatchArgs<T> stage_args(wombat_weno_batch_t *b, int s, T *u0, T *us, T *acc, T *out, double bw, double cw)
+{
+    BatchArgs<T> a;
+    a.pd = b->pd;
+    a.order = b->order;
+    a.npatch = (int)(b->dims.size() / 3);
+    a.counter = b->counters + s;
+    a.u0 = u0;
+    a.us = us;
+    a.acc = acc;
+    a.out = out;
+    a.scratch = (T *)b->scratch;
+    a.slot_elems = b->slot_elems;
+    a.dt = b->dt;
+    a.flag = b->flag;
+    a.cfl = b->cfg.cfl;
+    a.s = s;
+    a.bw = bw;
+    a.cw = cw;
+    a.P = ww::Phys{ b->cfg.gamma, b->cfg.eps, 1.0 / (b->cfg.gamma - 1.0) };
+    return a;
+}
+
+template <typename T>
 int launch_step_t(wombat_weno_batch_t *b, T *u, hipStream_t st)
 {
     static const double bw[4] = { 1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 0.0 };
@@ -168,27 +192,38 @@ int launch_step_t(wombat_weno_batch_t *b, T *u, hipStream_t st)
     T *in[4] = { u, A, B, A };
     T *out[4] = { A, B, A, u };
     WB_CHECK(b, ww::launch_batch_reset(b->counters, 4, st));
-    for (int s = 0; s < 4; ++s) {
-        BatchArgs<T> a;
-        a.pd = b->pd;
-        a.order = b->order;
-        a.npatch = (int)(b->dims.size() / 3);
-        a.counter = b->counters + s;
-        a.u0 = u;
-        a.us = in[s];
-        a.acc = acc;
-        a.out = out[s];
-        a.scratch = (T *)b->scratch;
-        a.slot_elems = b->slot_elems;
-        a.dt = b->dt;
-        a.flag = b->flag;
-        a.cfl = b->cfg.cfl;
-        a.s = s;
-        a.bw = bw[s];
-        a.cw = cw[s];
-        a.P = ww::Phys{ b->cfg.gamma, b->cfg.eps, 1.0 / (b->cfg.gamma - 1.0) };
-        WB_CHECK(b, ww::launch_batch_stage<T>(a, b->ft, b->nblocks, st));
-    }
+    for (int s = 0; s < 4; ++s)
+        WB_CHECK(b, ww::launch_batch_stage<T>(stage_args<T>(b, s, u, in[s], acc, out[s], bw[s], cw[s]), b->ft,
+                                              b->nblocks, st));
+    return WW_OK;
+}
+
+// Autotuner set-up: A = a copy of u, then stage 0 of a step from A (which
+// computes every patch's dt and leaves U_2 in B).
+template <typename T>
+int tune_prepare_t(wombat_weno_batch_t *b, const T *u)
+{
+    T *A = (T *)b->work[0], *B = (T *)b->work[1], *acc = (T *)b->work[2];
+    WB_CHECK(b, hipMemcpyAsync(A, u, b->esize * b->arena, hipMemcpyDeviceToDevice, b->st));
+    WB_CHECK(b, ww::launch_batch_reset(b->counters, 4, b->st));
+    WB_CHECK(b, ww::launch_batch_stage<T>(stage_args<T>(b, 0, A, A, acc, B, 1.0 / 6.0, 0.5), b->ft, b->nblocks,
+                                          b->st));
+    return WW_OK;
+}
+
+// One timed launch of the second stage's form on (u0 = A, us = B, acc), with
+// zero RK weights: acc and out = A keep their values, so every launch does
+// the same work.
+template <typename T>
+int tune_stage_t(wombat_weno_batch_t *b, float *ms)
+{
+    T *A = (T *)b->work[0], *B = (T *)b->work[1], *acc = (T *)b->work[2];
+    WB_CHECK(b, ww::launch_batch_reset(b->counters + 1, 1, b->st));
+    WB_CHECK(b, hipEventRecord(b->ev[0], b->st));
+    WB_CHECK(b, ww::launch_batch_stage<T>(stage_args<T>(b, 1, A, B, acc, A, 0.0, 0.0), b->ft, b->nblocks, b->st));
+    WB_CHECK(b, hipEventRecord(b->ev[1], b->st));
+    WB_CHECK(b, hipEventSynchronize(b->ev[1]));
+    WB_CHECK(b, hipEventElapsedTime(ms, b->ev[0], b->ev[1]));
     return WW_OK;
 }
 
@@ -316,14 +351,15 @@ int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int3
         delete b;
         return bfail(nullptr, WW_ERR_OOM, std::string("device allocation failed: ") + what);
     };
+    ww::alloc_hook_reset();
     for (int i = 0; i < 3; ++i)
-        if (hipMalloc(&b->work[i], b->esize * b->arena) != hipSuccess) { b->work[i] = nullptr; return fail_oom("work arenas"); }
-    if (hipMalloc(&b->scratch, b->esize * b->slot_elems * b->maxblocks) != hipSuccess) { b->scratch = nullptr; return fail_oom("face scratch"); }
-    if (hipMalloc((void **)&b->pd, sizeof(PatchDesc) * npatch) != hipSuccess) { b->pd = nullptr; return fail_oom("patch table"); }
-    if (hipMalloc((void **)&b->order, sizeof(int) * npatch) != hipSuccess) { b->order = nullptr; return fail_oom("patch order"); }
-    if (hipMalloc((void **)&b->counters, sizeof(int32_t) * 4) != hipSuccess) { b->counters = nullptr; return fail_oom("work counters"); }
-    if (hipMalloc((void **)&b->dt, sizeof(double) * npatch) != hipSuccess) { b->dt = nullptr; return fail_oom("dt"); }
-    if (hipMalloc((void **)&b->flag, sizeof(int32_t) * npatch) != hipSuccess) { b->flag = nullptr; return fail_oom("flags"); }
+        if (ww::dev_alloc(&b->work[i], b->esize * b->arena) != hipSuccess) return fail_oom("work arenas");
+    if (ww::dev_alloc(&b->scratch, b->esize * b->slot_elems * b->maxblocks) != hipSuccess) return fail_oom("face scratch");
+    if (ww::dev_alloc((void **)&b->pd, sizeof(PatchDesc) * npatch) != hipSuccess) return fail_oom("patch table");
+    if (ww::dev_alloc((void **)&b->order, sizeof(int) * npatch) != hipSuccess) return fail_oom("patch order");
+    if (ww::dev_alloc((void **)&b->counters, sizeof(int32_t) * 4) != hipSuccess) return fail_oom("work counters");
+    if (ww::dev_alloc((void **)&b->dt, sizeof(double) * npatch) != hipSuccess) return fail_oom("dt");
+    if (ww::dev_alloc((void **)&b->flag, sizeof(int32_t) * npatch) != hipSuccess) return fail_oom("flags");
     std::vector<int> order;
     make_order(b->dims, order);
     if (hipMemcpy(b->pd, b->hpd.data(), sizeof(PatchDesc) * npatch, hipMemcpyHostToDevice) != hipSuccess ||
@@ -433,31 +469,30 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
         if (best_ms) *best_ms = -1.0;
         return set_shape(b, ft, bpc);
     }
-    // Time one full step of every shape on a private copy of the state, so
-    // the caller's arena is not modified (the copy is this set-up call's only
-    // device allocation, freed before it returns).
+    // Every shape is timed on the same work: a copy of the state in the work
+    // arenas, advanced through stage 0 once; then per shape one untimed and
+    // five timed launches of stage 1 with zero RK weights, ranked by the
+    // median.  No allocation.
+    const bool f64 = b->cfg.precision == WW_FP64;
+    rc = f64 ? tune_prepare_t<double>(b, (const double *)d_arena) : tune_prepare_t<float>(b, (const float *)d_arena);
+    if (rc) return rc;
     double best = 1e300;
     int bft = 4, bb = 1;
     const int fts[4] = { 4, 8, 12, 16 };
+    constexpr int NT = 5;
     for (int fi = 0; fi < 4; ++fi)
         for (int c = 1; c <= 4; ++c) {
             rc = set_shape(b, fts[fi], c);
             if (rc) return rc;
             if (b->bpc != c) continue;          // beyond the occupancy limit
-            void *u = nullptr;
-            WB_CHECK(b, hipMalloc(&u, b->esize * b->arena));
-            hipError_t e = hipMemcpyAsync(u, d_arena, b->esize * b->arena, hipMemcpyDeviceToDevice, b->st);
-            if (e == hipSuccess) rc = launch_step(b, u, b->st);    // warm-up
-            if (e == hipSuccess && !rc) e = hipEventRecord(b->ev[0], b->st);
-            if (e == hipSuccess && !rc) rc = launch_step(b, u, b->st);
-            if (e == hipSuccess && !rc) e = hipEventRecord(b->ev[1], b->st);
-            if (e == hipSuccess && !rc) e = hipEventSynchronize(b->ev[1]);
-            float ms = 0.0f;
-            if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, b->ev[0], b->ev[1]);
-            (void)hipFree(u);
-            if (rc) return rc;
-            if (e != hipSuccess) return bhip(b, e, "autotune timing");
-            if (ms < best) { best = ms; bft = fts[fi]; bb = c; }
+            float t[NT + 1];
+            for (int r = 0; r <= NT; ++r) {
+                rc = f64 ? tune_stage_t<double>(b, &t[r]) : tune_stage_t<float>(b, &t[r]);
+                if (rc) return rc;
+            }
+            std::sort(t + 1, t + NT + 1);
+            const double med = t[1 + NT / 2];
+            if (med < best) { best = med; bft = fts[fi]; bb = c; }
         }
     rc = set_shape(b, bft, bb);
     if (rc) return rc;

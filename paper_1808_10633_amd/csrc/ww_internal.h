@@ -4,7 +4,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/wombat_weno.h"
+
 namespace ww {
+
+// Every device and pinned-host allocation of the library goes through these
+// two functions, which count them (wombat_weno_alloc_count) and honour the
+// WOMBAT_WENO_FAIL_ALLOC test hook (the k-th allocation after the latest
+// init or batch init fails).
+hipError_t dev_alloc(void **p, size_t bytes);
+hipError_t host_alloc(void **p, size_t bytes);
+void alloc_hook_reset();
+long long alloc_total();
 
 // Geometry of one padded state array (u[v][k][j][i], i fastest).
 struct Geom {
@@ -31,6 +44,16 @@ struct FaceBox {
 };
 constexpr int NFC = 7;   // stored face-flux components
 
+// Geometry of a box of n[3] interior cells of widths dl[3] (an axis with
+// n == 1 is inactive) and its three face boxes.
+void box_geom(const int n[3], const double dl[3], Geom &G, FaceBox F[3]);
+
+// Checks of a configuration shared by every entry point that takes one:
+// WW_OK or WW_ERR_INVALID_ARG with the reason in why.
+int validate_config(const wombat_weno_config *c, std::string &why);
+// Message of a failure without a context (wombat_weno_last_error(NULL)).
+void set_global_error(const std::string &msg);
+
 struct Phys {
     double gamma, eps;
     double igm1;       // 1 / (gamma - 1)
@@ -56,10 +79,12 @@ struct StageCoef {
     double a0 = 0.0;   // mode 2: weight of u0
     double a1 = 0.0;   // mode 2: weight of us
 };
+// odelta, osv: out[v] of the cell at state index id is written at
+// out[id + odelta + v * osv] (defaults: the layout of the other arrays).
 template <typename T>
 hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const T *fx,
                          const T *fy, const T *fz, const FaceBox *F, const Geom &G,
-                         const StageCoef &c, hipStream_t st);
+                         const StageCoef &c, hipStream_t st, long odelta = 0, long osv = 0);
 
 template <typename T>
 hipError_t launch_ghosts(T *u, const Geom &G, int axis, const int bc[6], hipStream_t st);

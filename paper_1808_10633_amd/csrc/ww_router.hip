@@ -35,10 +35,6 @@ __device__ __forceinline__ short f2bf(float x)
     u += 0x7fffu + ((u >> 16) & 1u);      // round to nearest even
     return (short)(u >> 16);
 }
-__device__ __forceinline__ float bf2f(short h)
-{
-    return __uint_as_float(((unsigned)(unsigned short)h) << 16);
-}
 
 // The MLP in MFMA operand layout for this lane (l = lane, r = l%16, q = l/16).
 struct MlpRegs {
@@ -134,10 +130,8 @@ __device__ __forceinline__ bf4 pack_bf4(float a, float b, float c, float d)
 }
 
 // Forward pass of 16 samples, rows g[m*XS + k] (BF16), m = 0..15; returns
-// the logit of sample l%16 (in every lane).  If a1s/a2s are given, the
-// pre-activations (with bias) of sample m are stored at [(16 st + m)*32 ..].
-__device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R, float *a1s, float *a2s,
-                                           int st)
+// the logit of sample l%16 (in every lane).
+__device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R)
 {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
     f4 z1[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
@@ -154,7 +148,6 @@ __device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R, flo
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float a = z1[ot][i] + R.b1[ot][i];
-            if (a1s) a1s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
             h1[ot][i] = f2bf(fmaxf(a, 0.f));
         }
     f4 z2[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
@@ -169,7 +162,6 @@ __device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R, flo
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float a = z2[ot][i] + R.b2[ot][i];
-            if (a2s) a2s[(16 * st + r) * NH + 16 * ot + 4 * q + i] = a;
             part += R.w3[ot][i] * fmaxf(a, 0.f);
         }
     part += __shfl_xor(part, 16);
@@ -179,11 +171,10 @@ __device__ __forceinline__ float mlp_group(const short *g, const MlpRegs &R, flo
 
 // Forward pass of the 64 samples of this wave, rows xs[m*XS + k] (BF16),
 // m = 0..63.  lg[st] receives the logit of sample 16*st + l%16.
-__device__ __forceinline__ void mlp_wave(const short *xs, const MlpRegs &R, float (&lg)[4],
-                                         float *a1s, float *a2s)
+__device__ __forceinline__ void mlp_wave(const short *xs, const MlpRegs &R, float (&lg)[4])
 {
 #pragma unroll
-    for (int st = 0; st < 4; ++st) lg[st] = mlp_group(xs + 16 * st * XS, R, a1s, a2s, st);
+    for (int st = 0; st < 4; ++st) lg[st] = mlp_group(xs + 16 * st * XS, R);
 }
 
 __device__ __forceinline__ float pick4(const float (&v)[4], int i)
@@ -286,83 +277,194 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(const float *__restrict_
     load_mlp(th, R);
     const int w = tid >> 6, l = tid & 63;
     float lg[4];
-    mlp_wave(xs + w * 64 * XS, R, lg, nullptr, nullptr);
+    mlp_wave(xs + w * 64 * XS, R, lg);
     const long g = base + tid;
     if (g < n) logit[g] = pick4(lg, l >> 4);
 }
 
-// Gradient of the mean binary cross-entropy over n samples: per block of
-// 128 samples, the forward pass on MFMA, then the backward pass in FP32:
-// per-sample deltas, then every parameter's sum over the block's samples.
-// part[b][0..NPARAM-1] = gradient sums, part[b][NPARAM] = loss sum.
+// Gradient of the mean binary cross-entropy over n samples, 128 samples per
+// block (two waves of 64), every product on MFMA (BF16 operands, FP32
+// accumulation):
+//   forward   Z1^T = W1 X^T, Z2^T = W2 H1^T (as in inference), logit in FP32;
+//   deltas    g = (sigmoid(logit) - t) / n, D2 = w3 g [z2 > 0] (per sample),
+//             D1^T = W2^T D2^T, masked by [z1 > 0]: the C-layout registers of
+//             D2^T are the B operand of this product (no shuffles), and the
+//             result lands in the layout of Z1^T, whose mask sits in the same
+//             registers;
+//   weights   dW1 | db1 = D1^T [X | 1], dW2 | db2 = D2^T [H1 | 1]: products
+//             over the block's 128 samples (K = samples), with a row of ones
+//             appended to the sample-contiguous LDS copies of X and H1 so the
+//             bias gradients come out of the same MFMAs; dw3 = g^T H2 and
+//             db3 = sum g are reduced across lanes in FP32.
+// Rounding points (mirrored by the element-wise test): X, W1, W2, H1 = relu(z1),
+// D2 and the masked D1 are rounded to BF16; z1, z2, H2, the logit, g and every
+// sum are FP32.  part[b][0..NPARAM-1] = the block's gradient sums,
+// part[b][NPARAM] = its loss sum.
+constexpr int TS = 136;          // LDS row stride (BF16 elements) of the sample-contiguous copies
+
 __global__ __launch_bounds__(128) void mlp_grad_kernel(const float *__restrict__ th,
                                                        const float *__restrict__ X,
                                                        const float *__restrict__ t, int n,
                                                        float invn, float *__restrict__ part)
 {
-    __shared__ short xs[128 * XS];
-    __shared__ float a1s[128 * NH], a2s[128 * NH], d1s[128 * NH], d2s[128 * NH];
-    __shared__ float gs[128], ls[128];
+    __shared__ short xs[128 * XS];       // [sample][feature]: forward B operand
+    __shared__ short xT[64 * TS];        // [feature | ones | zeros][sample]
+    __shared__ short h1T[48 * TS];       // [hidden 1 | ones | zeros][sample]
+    __shared__ short d1T[32 * TS], d2T[32 * TS];
+    __shared__ float red[2][NH + 2];
     const int tid = threadIdx.x;
     const long base = (long)blockIdx.x * 128;
     for (int e = tid; e < 128 * NIN; e += 128) {
         const int m = e / NIN, k = e - m * NIN;
         const long g = base + m;
-        xs[m * XS + k] = g < n ? f2bf(X[g * NIN + k]) : (short)0;
+        const short v = g < n ? f2bf(X[g * NIN + k]) : (short)0;
+        xs[m * XS + k] = v;
+        xT[k * TS + m] = v;
+    }
+    const short one = f2bf(1.0f);
+    for (int e = tid; e < 16 * 128; e += 128) {
+        const int rr = e >> 7, m = e & 127;
+        xT[(NIN + rr) * TS + m] = rr == 0 ? one : (short)0;
+        h1T[(NH + rr) * TS + m] = rr == 0 ? one : (short)0;
     }
     __syncthreads();
     MlpRegs R;
     load_mlp(th, R);
-    const int w = tid >> 6, l = tid & 63;
-    float lg[4];
-    mlp_wave(xs + w * 64 * XS, R, lg, a1s + w * 64 * NH, a2s + w * 64 * NH);
-    const float z = pick4(lg, l >> 4);
-    __syncthreads();
-    const int m = tid;
-    const long gi = base + m;
-    float g = 0.f, lo = 0.f;
-    if (gi < n) {
-        const float tt = t[gi];
-        const float y = 1.0f / (1.0f + expf(-z));
-        g = (y - tt) * invn;
-        lo = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - tt * z;
+    const int w = tid >> 6, l = tid & 63, r = l & 15, q = l >> 4;
+    // W2^T in A-operand order: tile (jt, kt), lane holds W2^T[16jt + r][16kt + 4q + i]
+    bf4 a2t[2][2];
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a2t[jt][kt][i] = f2bf(th[OW2 + (16 * kt + 4 * q + i) * NH + 16 * jt + r]);
+    float gw3[2][4] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+    float gb3 = 0.f, gl = 0.f;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int col = 64 * w + 16 * st + r;          // this lane's sample within the block
+        const short *gx = xs + (64 * w + 16 * st) * XS;
+        f4 z1[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+        for (int kt = 0; kt < 3; ++kt) {
+            const bf4 bx = *(const bf4 *)(gx + r * XS + 16 * kt + 4 * q);
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot)
+                z1[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[ot][kt], bx, z1[ot], 0, 0, 0);
+        }
+        bf4 h1[2];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                z1[ot][i] += R.b1[ot][i];
+                h1[ot][i] = f2bf(fmaxf(z1[ot][i], 0.f));
+                h1T[(16 * ot + 4 * q + i) * TS + col] = h1[ot][i];
+            }
+        f4 z2[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot)
+                z2[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[ot][kt], h1[kt], z2[ot], 0, 0, 0);
+        float zl = 0.f;
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                z2[ot][i] += R.b2[ot][i];
+                zl += R.w3[ot][i] * fmaxf(z2[ot][i], 0.f);
+            }
+        zl += __shfl_xor(zl, 16);
+        zl += __shfl_xor(zl, 32);
+        const float z = zl + R.b3;                     // logit of sample `col` (every q)
+        const long gi = base + col;
+        float g = 0.f, lo = 0.f;
+        if (gi < n) {
+            const float tt = t[gi];
+            g = (1.0f / (1.0f + expf(-z)) - tt) * invn;
+            lo = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - tt * z;
+        }
+        if (q == 0) { gb3 += g; gl += lo; }
+        bf4 d2[2];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float h2 = fmaxf(z2[ot][i], 0.f);
+                gw3[ot][i] += g * h2;
+                d2[ot][i] = f2bf(z2[ot][i] > 0.f ? R.w3[ot][i] * g : 0.f);
+                d2T[(16 * ot + 4 * q + i) * TS + col] = d2[ot][i];
+            }
+        f4 d1[2] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int jt = 0; jt < 2; ++jt)
+                d1[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2t[jt][kt], d2[kt], d1[jt], 0, 0, 0);
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                d1T[(16 * jt + 4 * q + i) * TS + col] = f2bf(z1[jt][i] > 0.f ? d1[jt][i] : 0.f);
     }
-    gs[m] = g;
-    ls[m] = lo;
-    for (int o = 0; o < NH; ++o) d2s[m * NH + o] = a2s[m * NH + o] > 0.f ? th[OW3 + o] * g : 0.f;
-    for (int j = 0; j < NH; ++j) {
-        float s = 0.f;
-        for (int o = 0; o < NH; ++o) s += th[OW2 + o * NH + j] * d2s[m * NH + o];
-        d1s[m * NH + j] = a1s[m * NH + j] > 0.f ? s : 0.f;
+    // dw3, db3 and the loss: sums over the 16 lanes of a row group, then the two waves
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) gw3[ot][i] += __shfl_xor(gw3[ot][i], m);
+        gb3 += __shfl_xor(gb3, m);
+        gl += __shfl_xor(gl, m);
+    }
+    if (r == 0) {
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[w][16 * ot + 4 * q + i] = gw3[ot][i];
+        if (q == 0) { red[w][NH] = gb3; red[w][NH + 1] = gl; }
     }
     __syncthreads();
     float *pb = part + (long)blockIdx.x * (NPARAM + 1);
-    for (int p = tid; p < NPARAM; p += 128) {
-        float acc = 0.f;
-        if (p < OB1) {
-            const int o = p / NIN, k = p - o * NIN;
-            for (int s = 0; s < 128; ++s) acc += d1s[s * NH + o] * bf2f(xs[s * XS + k]);
-        } else if (p < OW2) {
-            const int o = p - OB1;
-            for (int s = 0; s < 128; ++s) acc += d1s[s * NH + o];
-        } else if (p < OB2) {
-            const int o = (p - OW2) / NH, k = (p - OW2) - o * NH;
-            for (int s = 0; s < 128; ++s) acc += d2s[s * NH + o] * fmaxf(a1s[s * NH + k], 0.f);
-        } else if (p < OW3) {
-            const int o = p - OB2;
-            for (int s = 0; s < 128; ++s) acc += d2s[s * NH + o];
-        } else if (p < OB3) {
-            const int o = p - OW3;
-            for (int s = 0; s < 128; ++s) acc += gs[s] * fmaxf(a2s[s * NH + o], 0.f);
-        } else {
-            for (int s = 0; s < 128; ++s) acc += gs[s];
-        }
-        pb[p] = acc;
+    if (tid < NH) pb[OW3 + tid] = red[0][tid] + red[1][tid];
+    if (tid == NH) pb[OB3] = red[0][NH] + red[1][NH];
+    if (tid == NH + 1) pb[NPARAM] = red[0][NH + 1] + red[1][NH + 1];
+    // weight gradients over the 128 samples: wave w takes output rows 16w..16w+15
+    f4 g1[4] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f },
+                 { 0.f, 0.f, 0.f, 0.f } };
+    f4 g2[3] = { { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f }, { 0.f, 0.f, 0.f, 0.f } };
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        const int s0 = 16 * ks + 4 * q;
+        const bf4 a1 = *(const bf4 *)(d1T + (16 * w + r) * TS + s0);
+        const bf4 a2 = *(const bf4 *)(d2T + (16 * w + r) * TS + s0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            g1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, *(const bf4 *)(xT + (16 * nt + r) * TS + s0),
+                                                               g1[nt], 0, 0, 0);
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt)
+            g2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, *(const bf4 *)(h1T + (16 * nt + r) * TS + s0),
+                                                               g2[nt], 0, 0, 0);
     }
-    if (tid == 0) {
-        float s = 0.f;
-        for (int i = 0; i < 128; ++i) s += ls[i];
-        pb[NPARAM] = s;
+    // lane holds D[row 16w + 4q + i][column 16nt + r]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int o = 16 * w + 4 * q + i;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int k = 16 * nt + r;
+            if (k < NIN) pb[OW1 + o * NIN + k] = g1[nt][i];
+            else if (k == NIN) pb[OB1 + o] = g1[nt][i];
+        }
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt) {
+            const int j = 16 * nt + r;
+            if (j < NH) pb[OW2 + o * NH + j] = g2[nt][i];
+            else if (j == NH) pb[OB2 + o] = g2[nt][i];
+        }
     }
 }
 
@@ -564,8 +666,8 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const float z0 = mlp_group(g, R, nullptr, nullptr, 0);
-            const float z1 = mlp_group(g + 16 * XS, R, nullptr, nullptr, 0);
+            const float z0 = mlp_group(g, R);
+            const float z1 = mlp_group(g + 16 * XS, R);
             if ((lane >> 4) == 2 * h) lg = z0;
             if ((lane >> 4) == 2 * h + 1) lg = z1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -49,9 +49,11 @@ __global__ __launch_bounds__(256) void update_march_kernel(UpdArgs<T> a, int ntx
 template <typename T>
 hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const T *fx,
                          const T *fy, const T *fz, const FaceBox *F, const Geom &G,
-                         const StageCoef &c, hipStream_t st)
+                         const StageCoef &c, hipStream_t st, long odelta, long osv)
 {
     UpdArgs<T> a;
+    a.odelta = odelta;
+    a.osv = osv > 0 ? osv : G.sv;
     a.u0 = u0; a.acc_in = acc_in; a.acc_out = acc_out; a.out = out;
     a.ff[0] = fx; a.ff[1] = fy; a.ff[2] = fz;
     for (int d = 0; d < 3; ++d) a.fb[d] = F[d];
@@ -74,10 +76,10 @@ hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const
 template hipError_t launch_update<double>(const double *, const double *, double *, double *,
                                           const double *, const double *, const double *,
                                           const FaceBox *, const Geom &, const StageCoef &,
-                                          hipStream_t);
+                                          hipStream_t, long, long);
 template hipError_t launch_update<float>(const float *, const float *, float *, float *,
                                          const float *, const float *, const float *,
                                          const FaceBox *, const Geom &, const StageCoef &,
-                                         hipStream_t);
+                                         hipStream_t, long, long);
 
 }  // namespace ww

@@ -27,6 +27,8 @@ struct UpdArgs {
     FaceBox fb[3];
     Geom G;
     StageCoef c;
+    long odelta;       // out[v] of the cell at index id sits at id + odelta + v * osv
+    long osv;          // (odelta = 0, osv = G.sv: out has the layout of the other arrays)
 };
 
 template <typename T>
@@ -80,9 +82,11 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
 {
     const StageCoef &c = a.c;
     const long sv = a.G.sv;
+    T *const out = a.out + (id + a.odelta);
+    const long osv = a.osv;
     if (c.mode == 0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) a.out[id + v * sv] = L[v];
+        for (int v = 0; v < 8; ++v) out[v * osv] = L[v];
         return;
     }
     const T bdt = T(c.bdt), cdt = T(c.cdt);
@@ -91,10 +95,10 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
         if (c.a1 != 0.0) {
 #pragma unroll
             for (int v = 0; v < 8; ++v)
-                a.out[id + v * sv] = a0 * a.u0[id + v * sv] + a1 * a.acc_in[id + v * sv] + cdt * L[v];
+                out[v * osv] = a0 * a.u0[id + v * sv] + a1 * a.acc_in[id + v * sv] + cdt * L[v];
         } else {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) a.out[id + v * sv] = a0 * a.u0[id + v * sv] + cdt * L[v];
+            for (int v = 0; v < 8; ++v) out[v * osv] = a0 * a.u0[id + v * sv] + cdt * L[v];
         }
         return;
     }
@@ -103,7 +107,7 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
         for (int v = 0; v < 8; ++v) {
             T u0 = a.u0[id + v * sv];
             a.acc_out[id + v * sv] = u0 + bdt * L[v];
-            a.out[id + v * sv] = u0 + cdt * L[v];
+            out[v * osv] = u0 + cdt * L[v];
         }
     } else if (c.s < 3) {
 #pragma unroll
@@ -111,11 +115,11 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
             T u0 = a.u0[id + v * sv];
             T ac = a.acc_in[id + v * sv];
             a.acc_out[id + v * sv] = ac + bdt * L[v];
-            a.out[id + v * sv] = u0 + cdt * L[v];
+            out[v * osv] = u0 + cdt * L[v];
         }
     } else {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) a.out[id + v * sv] = a.acc_in[id + v * sv] + cdt * L[v];
+        for (int v = 0; v < 8; ++v) out[v * osv] = a.acc_in[id + v * sv] + cdt * L[v];
     }
 }
 

@@ -47,3 +47,23 @@ if __name__ == "__main__":
     for k, v in STEPS.items():
         print(f"{v:6d}  {k}")
     print(f"{flops_per_interface():6d}  total per interface")
+
+
+# The textbook formulation of the same interface (dense 7x7 left and right
+# eigenvector products on 12 projected vectors, the mean state, the LF split,
+# the weights and the back-projection), about 2.35 kflop: a second yardstick
+# for the sweep's fraction of peak that does not credit the sparse
+# primitive-variable rows.
+DENSE_FLOPS_PER_INTERFACE = 2350
+
+
+def update_bytes_per_cell(esize: int, integrator: str = "rk4") -> float:
+    """Algorithmic HBM bytes per interior cell of one launch of the flux
+    difference / CT / RK update, averaged over the stage forms of a step:
+    the 7 stored face components of the three sweeps (one face per cell and
+    direction) and the RK arrays: RK4 stages read u0 and write acc, out;
+    read u0, acc and write acc, out (twice); read acc and write out
+    (3, 4, 4, 2 arrays: 13/4 on average)."""
+    faces = 7 * 3 * esize
+    arrays = {"rk4": 13 / 4, "ssprk3": (2 + 3 + 3) / 3}[integrator]
+    return faces + arrays * 8 * esize

@@ -24,7 +24,7 @@ WW_ERR_STATE = -7
 _NAMES = {0: "WW_OK", -1: "WW_ERR_INVALID_ARG", -2: "WW_ERR_UNSUPPORTED", -3: "WW_ERR_OOM",
           -4: "WW_ERR_HIP", -5: "WW_ERR_NONPHYSICAL", -6: "WW_ERR_USER_BC", -7: "WW_ERR_STATE"}
 
-ABI_VERSION = 4          # layout of Config below
+ABI_VERSION = 5          # layout of Config below
 WW_FP64 = 0
 WW_FP32_MIXED = 1
 WEIGHTS_JS, WEIGHTS_Z = 0, 1
@@ -42,7 +42,8 @@ class Config(C.Structure):
                 ("precision", C.c_int), ("bc", C.c_int * 6),
                 ("user_bc", USER_BC_FN), ("user_bc_ctx", C.c_void_p),
                 ("stream", C.c_void_p), ("device", C.c_int), ("weights", C.c_int),
-                ("integrator", C.c_int), ("lf_speed", C.c_int)]
+                ("integrator", C.c_int), ("lf_speed", C.c_int), ("learned", C.c_int),
+                ("slab_planes", C.c_int)]
 
 
 class WenoError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
         L.wombat_weno_sums.argtypes = [vp, vp, C.POINTER(d)]
         L.wombat_weno_divb.argtypes = [vp, vp, C.POINTER(d), C.POINTER(d)]
         L.wombat_weno_time_kernels.argtypes = [vp, vp, i32, C.POINTER(d)]
+        L.wombat_weno_alloc_count.restype = C.c_int64
         L.wombat_weno_batch_init.argtypes = [C.POINTER(Config), i32, C.POINTER(C.c_int32), C.POINTER(vp)]
         L.wombat_weno_batch_destroy.argtypes = [vp]
         L.wombat_weno_batch_destroy.restype = None
@@ -112,6 +114,11 @@ def lib():
     return _lib
 
 
+def alloc_count() -> int:
+    """Device and pinned-host allocations the library has made so far."""
+    return int(lib().wombat_weno_alloc_count())
+
+
 def last_error(ctx=None) -> str:
     s = lib().wombat_weno_last_error(ctx)
     return s.decode() if s else ""
@@ -120,7 +127,7 @@ def last_error(ctx=None) -> str:
 def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, cfl=0.4,
                 eps=1e-6, precision=WW_FP64, bc=(0, 0, 0, 0, 0, 0), user_bc=None,
                 stream=None, device=0, weights=WEIGHTS_JS, integrator=RK4,
-                lf_speed=LF_LOCAL) -> Config:
+                lf_speed=LF_LOCAL, learned=0, slab_planes=0) -> Config:
     cfg = Config()
     lib().wombat_weno_config_default(C.byref(cfg))
     cfg.nx, cfg.ny, cfg.nz, cfg.ng = nx, ny, nz, 3
@@ -137,6 +144,8 @@ def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, c
     cfg.weights = weights
     cfg.integrator = integrator
     cfg.lf_speed = lf_speed
+    cfg.learned = int(learned)
+    cfg.slab_planes = int(slab_planes)
     return cfg
 
 
@@ -222,9 +231,13 @@ class Context:
         _check(lib().wombat_weno_sums(self.h, self._ptr(u, "u"), out), self.h)
         return list(out)
 
+    KERNELS = ("ghosts", "sweep_x", "sweep_y", "sweep_z", "update_stage", "cfl", "update_rhs")
+
     def time_kernels(self, u, reps=10):
-        """Average ms per launch: ghosts, sweep x, y, z, update."""
-        out = (C.c_double * 5)()
+        """Average ms per launch, in the order of KERNELS: ghosts, sweeps x, y,
+        z, the update in the stage forms of a step (their mean), the CFL
+        reduction, the update writing L(U) only."""
+        out = (C.c_double * 7)()
         _check(lib().wombat_weno_time_kernels(self.h, self._ptr(u, "u"), int(reps), out), self.h)
         return list(out)
 

@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wombat_weno_abi_version() == 4 == wombat.ABI_VERSION
+    assert lib.wombat_weno_abi_version() == 5 == wombat.ABI_VERSION
 
 
 def _cfg(**kw):
@@ -145,3 +145,47 @@ def test_lf_speed_default_and_batched_rejects_global(lib):
     assert lib.wombat_weno_batch_init(C.byref(cfg), 1, dims, C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
     assert "LF" in lib.wombat_weno_batch_last_error(None).decode()
     assert h.value == 1234
+
+
+def test_learned_field_default_and_checks(lib):
+    cfg = _cfg()
+    assert cfg.learned == 0
+    cfg.learned = 2
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == wombat.WW_ERR_INVALID_ARG
+    assert "learned" in wombat.last_error()
+    # the learned form's buffers are for FP32 contexts of the paper's scheme:
+    # refused before any device work
+    h = C.c_void_p(1234)
+    for kw in (dict(learned=1), dict(learned=1, precision=wombat.WW_FP32_MIXED, weights=wombat.WEIGHTS_Z),
+               dict(learned=1, precision=wombat.WW_FP32_MIXED, integrator=wombat.SSPRK3),
+               dict(learned=1, precision=wombat.WW_FP32_MIXED, lf_speed=wombat.LF_GLOBAL)):
+        c2 = _cfg(**kw)
+        assert lib.wombat_weno_validate_config(C.byref(c2)) == 0
+        assert lib.wombat_weno_init(C.byref(c2), C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
+        assert h.value == 1234
+
+
+def test_alloc_count_is_exported(lib):
+    n0 = wombat.alloc_count()
+    assert n0 >= 0
+    # refused configurations allocate nothing
+    cfg = _cfg(nx=0)
+    h = C.c_void_p()
+    assert lib.wombat_weno_init(C.byref(cfg), C.byref(h)) == wombat.WW_ERR_INVALID_ARG
+    assert wombat.alloc_count() == n0
+
+
+def test_slab_planes_checks(lib):
+    assert _cfg().slab_planes == 0
+    for kw, frag in ((dict(slab_planes=2), "slab_planes"), (dict(slab_planes=-1), "slab_planes"),
+                     (dict(slab_planes=8, nz=1, dz=1.0), "z axis")):
+        cfg = _cfg(**kw)
+        assert lib.wombat_weno_validate_config(C.byref(cfg)) == wombat.WW_ERR_INVALID_ARG
+        assert frag in wombat.last_error()
+    h = C.c_void_p(1234)
+    for kw in (dict(slab_planes=8, integrator=wombat.SSPRK3), dict(slab_planes=8, lf_speed=wombat.LF_GLOBAL),
+               dict(slab_planes=8, learned=1, precision=wombat.WW_FP32_MIXED)):
+        cfg = _cfg(**kw)
+        assert lib.wombat_weno_validate_config(C.byref(cfg)) == 0
+        assert lib.wombat_weno_init(C.byref(cfg), C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
+        assert h.value == 1234

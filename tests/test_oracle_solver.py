@@ -339,3 +339,36 @@ def test_inclined_alfven_wave_accuracy(orc):
         ue, _ = I.alfven_wave_3d(n, t=T)
         errs.append(np.abs(g.interior(u) - g.interior(ue)).max())
     assert errs[1] < errs[0] / 3.5 and errs[1] < 1e-8, errs
+
+
+def test_dependency_cone_of_a_step(orc):
+    # One RK4 stage reads 3 cells along each axis (the six-cell stencils and
+    # CT's one-cell-across edge averages), so after a step (4 stages) the
+    # cells at least 12 from the faces of a block cut out of a periodic box
+    # and advanced with outflow faces equal the periodic run's, bit for bit.
+    # The config-2 GPU test compares two steps of such blocks (reach 24).
+    from paper_1808_10633_amd import inputs as I
+    n, reach, inner = 30, 12, 5
+    blk_n = 2 * reach + inner
+    u = I.turbulence((n, n, n), mach=1.0, beta=1.0, seed=77, kmax=5).numpy().copy()
+    g = orc.Grid(n, n, n, 1.0 / n, 1.0 / n, 1.0 / n)
+    dt = 0.5 * orc.cfl_dt(g, u)
+    full = u.copy()
+    orc.rk4_step(g, full, dt)
+    c = (7, 22, 13)
+    h = blk_n // 2
+    idx = [np.arange(cc - h, cc - h + blk_n) % n + 3 for cc in c]
+    blk = np.zeros((8, blk_n + 6, blk_n + 6, blk_n + 6))
+    blk[:, 3:-3, 3:-3, 3:-3] = u[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+    gb = orc.Grid(blk_n, blk_n, blk_n, 1.0 / n, 1.0 / n, 1.0 / n, bc=(1, 1, 1, 1, 1, 1))
+    orc.rk4_step(gb, blk, dt)
+    sel = [np.arange(cc - h + reach, cc - h + reach + inner) % n + 3 for cc in c]
+    want = full[:, sel[2]][:, :, sel[1]][:, :, :, sel[0]]
+    got = blk[:, 3 + reach:3 + reach + inner, 3 + reach:3 + reach + inner, 3 + reach:3 + reach + inner]
+    assert np.array_equal(got, want)
+    # one layer further out the outflow faces are felt (the reach is not
+    # smaller than 3 cells per stage)
+    sel2 = [np.arange(cc - h + reach - 1, cc - h + reach + inner + 1) % n + 3 for cc in c]
+    want2 = full[:, sel2[2]][:, :, sel2[1]][:, :, :, sel2[0]]
+    got2 = blk[:, 2 + reach:4 + reach + inner, 2 + reach:4 + reach + inner, 2 + reach:4 + reach + inner]
+    assert not np.array_equal(got2, want2)
