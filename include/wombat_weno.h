@@ -255,6 +255,26 @@ int wombat_weno_time_kernels(wombat_weno_t *ctx, void *d_u, int reps, double ms[
  * shows that calls after init allocate nothing. */
 int64_t wombat_weno_alloc_count(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * right-hand side of wombat_weno_rhs without a context.  cfg is validated as
+ * in wombat_weno_init (cfg->learned must be 0; the stream and device of cfg
+ * are used); d_u (its ghosts are filled) and d_dudt (interior written) are
+ * caller-owned device states of cfg's layout and precision, d_dudt must not
+ * alias d_u.  The face fluxes of the three sweeps (and, with WW_LF_GLOBAL,
+ * 57 KB of partial maxima) are kept in one fixed 64 MiB device array of the
+ * library, 256-byte aligned per buffer: boxes whose face fluxes exceed it
+ * (e.g. beyond ~70^3 in FP64 or ~90^3 in FP32) get WW_ERR_INVALID_ARG and a
+ * message.  The call allocates nothing (no hipMalloc, no pinned memory,
+ * nothing from the caller); each GPU it runs on holds its own copy of the
+ * array until the process ends.  Every buffer is written before it is read
+ * in a call, so no contents carry over between calls, but all calls on one
+ * GPU share the array: calls that overlap in time on one GPU (other streams,
+ * other threads) race.  Results equal wombat_weno_rhs's bit for bit.
+ * Asynchronous on cfg->stream.  Errors: WW_ERR_INVALID_ARG, WW_ERR_UNSUPPORTED,
+ * WW_ERR_USER_BC, WW_ERR_HIP (message in wombat_weno_last_error(NULL)). */
+int wombat_weno_rhs_noalloc(const wombat_weno_config *cfg, void *d_u, void *d_dudt);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent periodic patches (Sec. 2.2: the domain is
  * cut into patches with their own ghost zones that are computed

@@ -16,6 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwombat_weno.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["ww_api.hip", "ww_sweep.hip", "ww_update.hip", "ww_aux.hip", "ww_batch.hip", "ww_batch_api.hip",
+           "ww_noalloc.hip",
            "ww_router.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -86,6 +86,7 @@ def lib():
         L.wombat_weno_divb.argtypes = [vp, vp, C.POINTER(d), C.POINTER(d)]
         L.wombat_weno_time_kernels.argtypes = [vp, vp, i32, C.POINTER(d)]
         L.wombat_weno_alloc_count.restype = C.c_int64
+        L.wombat_weno_rhs_noalloc.argtypes = [C.POINTER(Config), vp, vp]
         L.wombat_weno_batch_init.argtypes = [C.POINTER(Config), i32, C.POINTER(C.c_int32), C.POINTER(vp)]
         L.wombat_weno_batch_destroy.argtypes = [vp]
         L.wombat_weno_batch_destroy.restype = None
@@ -117,6 +118,12 @@ def lib():
 def alloc_count() -> int:
     """Device and pinned-host allocations the library has made so far."""
     return int(lib().wombat_weno_alloc_count())
+
+
+def rhs_noalloc(cfg, u, dudt):
+    """wombat_weno_rhs_noalloc: L(u) into dudt for the configuration cfg
+    (a Config), without a context and without allocation."""
+    _check(lib().wombat_weno_rhs_noalloc(C.byref(cfg), C.c_void_p(u.data_ptr()), C.c_void_p(dudt.data_ptr())))
 
 
 def last_error(ctx=None) -> str:
