@@ -158,12 +158,13 @@ def roofline_sweep(ms_y, n, prec, opcount, peak):
             "dense_flop_per_interface": opcount.DENSE_FLOPS_PER_INTERFACE}
 
 
-def roofline_update(ms_u, n, prec, opcount):
-    """HBM roofline of the flux-difference/CT/RK update in its stage forms:
-    algorithmic bytes per launch (face fluxes + RK arrays, averaged over the
-    four stage forms) over the event-timed launch."""
+def roofline_update(ms_u, n, prec, opcount, fused_x=True):
+    """HBM roofline of the update in its stage forms: algorithmic bytes per
+    launch (averaged over the four stage forms; with the fused x sweep the
+    update carries constrained transport and B only) over the event-timed
+    launch."""
     es = 8 if prec == "fp64" else 4
-    bpc = opcount.update_bytes_per_cell(es)
+    bpc = opcount.update_bytes_per_cell(es, fused_x=fused_x)
     nbytes = bpc * n ** 3
     achieved = nbytes / (ms_u * 1e-3) / 1e9
     tr = MEASURED_UPDATE_TRAFFIC.get((update_source_hash(), prec, n))
@@ -171,19 +172,48 @@ def roofline_update(ms_u, n, prec, opcount):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
             "traffic_source": tr["profile"] if tr else None,
-            "kernel": f"update_march_kernel<{'double' if es == 8 else 'float'}> (RK stage forms)",
+            "kernel": f"update_march_kernel<{'double' if es == 8 else 'float'}, {'true' if fused_x else 'false'}, "
+                      f"false> (RK stage forms{', B only' if fused_x else ''})",
             "ms": ms_u, "algorithmic_bytes_per_cell": bpc, "cells_per_launch": n ** 3}
 
 
-def rooflines(ms, n, prec, opcount, peak):
-    """Both rooflines; the dominant kernel is the one with the largest time
-    per step (each sweep direction and the update run once per stage)."""
+def roofline_xfused(ms_x, n, prec, opcount, peak):
+    """The x sweep with the rho, m, E update fused in: it does the sweep's
+    flux arithmetic and moves the hydro update's data.  HBM roofline on its
+    algorithmic bytes per launch (the bound it is closer to), with the VALU
+    fraction of its flux arithmetic beside it."""
+    es = 8 if prec == "fp64" else 4
+    bpc = opcount.fused_x_bytes_per_cell(es)
+    nbytes = bpc * n ** 3
+    achieved = nbytes / (ms_x * 1e-3) / 1e9
+    nface = (n + 1) * (n + 2) * (n + 2)
+    tflops = opcount.flops_per_interface() * nface / (ms_x * 1e-3) / 1e12
+    tr = MEASURED_TRAFFIC.get((sweep_source_hash(), prec + "_xfused", n))
+    traffic = (tr["read"] + tr["write"]) if tr else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+            "traffic_source": tr["profile"] if tr else None,
+            "measured_hbm_frac": round(traffic / (ms_x * 1e-3) / HBM_PEAK, 4) if tr else None,
+            "kernel": f"sweep_xfused_kernel<{'double' if es == 8 else 'float'}> (x sweep + rho, m, E update, "
+                      "RK stage forms)",
+            "ms": ms_x, "algorithmic_bytes_per_cell": bpc, "cells_per_launch": n ** 3,
+            "valu_achieved_tflops": round(tflops, 3), "valu_frac": round(tflops / peak, 4)}
+
+
+def rooflines(ms, n, prec, opcount, peak, fused_x=True):
+    """Rooflines of the sweep (y), the fused x sweep and the update; the
+    dominant kernel is the one with the largest time per step (each sweep
+    direction and the update run once per stage)."""
     sweep = roofline_sweep(ms[2], n, prec, opcount, peak)
-    upd = roofline_update(ms[4], n, prec, opcount)
+    upd = roofline_update(ms[4], n, prec, opcount, fused_x)
+    xf = roofline_xfused(ms[1], n, prec, opcount, peak) if fused_x else None
     longest = max(("sweep_x", ms[1]), ("sweep_y", ms[2]), ("sweep_z", ms[3]), ("update_stage", ms[4]),
                   key=lambda t: t[1])[0]
-    dom = upd if longest == "update_stage" else sweep
-    return dict(dom, dominant=longest), {"sweep_y": sweep, "update": upd}
+    dom = {"update_stage": upd, "sweep_x": xf if fused_x else sweep}.get(longest, sweep)
+    out = {"sweep_y": sweep, "update": upd}
+    if xf:
+        out["sweep_x_fused"] = xf
+    return dict(dom, dominant=longest), out
 
 
 def batched_form(a, wombat, inputs, opcount):
@@ -329,10 +359,14 @@ def precision_box(a, wombat, inputs):
 
     dts_out = []
     u64 = ic()
+    # the FP32 run's initial state waits in host memory (regenerating it next
+    # to the FP64 result would not fit: the generator's FFTs take ~150 GB)
+    host32 = u64.float().cpu()
+    torch.cuda.empty_cache()
     print(f"[bench] {n}^3 FP64 initial state ready", file=sys.stderr, flush=True)
     r64 = run(u64, wombat.WW_FP64, None, "fp64")
-    u32 = ic().float().contiguous()
-    torch.cuda.empty_cache()
+    u32 = host32.cuda()
+    del host32
     r32 = run(u32, wombat.WW_FP32_MIXED, dts_out, "fp32")
     l1, linf = [], []
     g = 3

@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define WOMBAT_WENO_ABI_VERSION 5
+#define WOMBAT_WENO_ABI_VERSION 6
 
 typedef enum {
     WW_OK = 0,
@@ -95,6 +95,17 @@ typedef enum { WW_RK4 = 0, WW_SSPRK3 = 1 } ww_integrator;
  * and stage); an ablation, single-grid operator only. */
 typedef enum { WW_LF_LOCAL = 0, WW_LF_GLOBAL = 1 } ww_lf_speed;
 typedef enum { WW_BC_PERIODIC = 0, WW_BC_OUTFLOW = 1, WW_BC_USER = 2 } ww_bc;
+/* Storage of B.  WW_B_CELL: cell-centred B; constrained transport advances
+ * each staggered face by -(curl E).n and the cell field by the mean of its
+ * two faces (the reading used throughout; invariant: the corner divergence).
+ * WW_B_FACE: staggered storage, the mesh of Ryu et al. (1998) that Sec. 2.1
+ * names: the B_d slot of a cell holds the normal field of its lower d-face
+ * (at i - 1/2 along d); the sweeps see the mean of a cell's two faces; each
+ * face advances by -(curl E).n from the same edge EMFs (invariant: the face
+ * divergence); an ablation, periodic boxes, single-grid operator only.  With
+ * B_cell = mean of the faces the two forms give the same cell field up to
+ * round-off. */
+typedef enum { WW_B_CELL = 0, WW_B_FACE = 1 } ww_b_storage;
 
 /* User boundary hook: called for each WW_BC_USER face (0..5 = -x,+x,-y,+y,
  * -z,+z) whenever ghosts are filled, after the built-in faces of the same
@@ -137,6 +148,8 @@ typedef struct {
                                 instead of three, and wombat_weno_stage may
                                 write its output over its input (added in ABI 5).
                                 Results are identical bit for bit.           */
+    int b_storage;           /* ww_b_storage (added in ABI 6); WW_B_FACE needs
+                                periodic faces and no slab_planes or router  */
 } wombat_weno_config;
 
 typedef struct wombat_weno wombat_weno_t;
@@ -146,7 +159,7 @@ int wombat_weno_abi_version(void);
 
 /* Fill *cfg with defaults: 32^3 unit box, ng 3, gamma 5/3, cfl 0.4,
  * eps 1e-6, WW_FP64, all faces periodic, null stream, device 0,
- * WW_WEIGHTS_JS, WW_RK4, WW_LF_LOCAL, learned 0, slab_planes 0.
+ * WW_WEIGHTS_JS, WW_RK4, WW_LF_LOCAL, learned 0, slab_planes 0, WW_B_CELL.
  * Returns WW_ERR_INVALID_ARG if cfg is NULL. */
 int wombat_weno_config_default(wombat_weno_config *cfg);
 
@@ -168,7 +181,9 @@ int64_t wombat_weno_state_elems(const wombat_weno_config *cfg);
  * byte per face of every sweep).  *out is written only on success.
  * Errors: WW_ERR_INVALID_ARG, WW_ERR_OOM, WW_ERR_HIP, WW_ERR_UNSUPPORTED
  * (cfg->learned with a precision or scheme the router does not serve;
- * slab_planes with WW_SSPRK3, WW_LF_GLOBAL or learned). */
+ * slab_planes with WW_SSPRK3, WW_LF_GLOBAL or learned; WW_B_FACE with a
+ * non-periodic face, slab_planes or learned).  WW_B_FACE adds one
+ * state-sized work array (the cell-centred state the sweeps read). */
 int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out);
 
 /* Release a context and its device memory.  NULL is allowed. */
@@ -183,8 +198,9 @@ const char *wombat_weno_last_error(const wombat_weno_t *ctx);
 int wombat_weno_fill_ghosts(wombat_weno_t *ctx, void *d_u);
 
 /* CFL time step dt = cfl / max over interior cells of
- * sum_d (|v_d| + c_f,d)/dx_d, reduced in FP64 on the device; waits for the
- * stream and writes *dt.  WW_ERR_NONPHYSICAL if any interior cell has
+ * sum_d (|v_d| + c_f,d)/dx_d, reduced in FP64 on the device (with
+ * WW_B_FACE, of the cell-centred state); waits for the stream and writes
+ * *dt.  WW_ERR_NONPHYSICAL if any interior cell has
  * rho <= 0, p <= 0 or a non-finite value (then *dt is not written). */
 int wombat_weno_cfl_dt(wombat_weno_t *ctx, const void *d_u, double *dt);
 
@@ -232,7 +248,9 @@ int wombat_weno_sums(wombat_weno_t *ctx, const void *d_u, double out[8]);
 /* Corner divergence of the cell-centred field: for each corner i+1/2 (and
  * j+1/2, k+1/2 on active axes), i = 0..n-1, the sum over active axes d of the
  * mean over the adjacent cell pairs of (B_d(+1) - B_d(0))/dx_d.  Fills the
- * ghosts of d_u first.  Writes max |div B| and its mean.  Synchronous. */
+ * ghosts of d_u first.  Writes max |div B| and its mean.  With WW_B_FACE:
+ * the face divergence sum_d (b_d(i+1/2) - b_d(i-1/2))/dx_d of every cell
+ * instead.  Synchronous. */
 int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1);
 
 /* Kernel timing: average device time in milliseconds per launch of each

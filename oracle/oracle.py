@@ -43,7 +43,7 @@ class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("gamma", C.c_double), ("cfl", C.c_double), ("eps", C.c_double),
-                ("bc", C.c_int * 6), ("weights", C.c_int), ("lf_global", C.c_int)]
+                ("bc", C.c_int * 6), ("weights", C.c_int), ("lf_global", C.c_int), ("b_face", C.c_int)]
 
 
 @dataclass
@@ -61,6 +61,7 @@ class Grid:
     bc: tuple = field(default_factory=lambda: (0, 0, 0, 0, 0, 0))   # 0 periodic, 1 outflow
     weights: int = 0          # 0: weights of eq. (3); 1: WENO-Z (ablation)
     lf_global: int = 0        # 0: LF speed per stencil; 1: per sweep over the box (ablation)
+    b_face: int = 0           # 0: cell-centred B; 1: staggered face-normal B in the B slots (ablation)
 
     def c(self) -> _Grid:
         g = _Grid(self.nx, self.ny, self.nz, self.dx, self.dy, self.dz,
@@ -69,6 +70,7 @@ class Grid:
             g.bc[i] = int(self.bc[i])
         g.weights = int(self.weights)
         g.lf_global = int(self.lf_global)
+        g.b_face = int(self.b_face)
         return g
 
     @property
@@ -150,6 +152,8 @@ def _load(path):
     L.orc_interface_flux_alpha.argtypes = [_dp, d, d, C.c_int, _dp, _dp]
     L.orc_sums.argtypes = [g, _dp, _dp]
     L.orc_divb.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
+    L.orc_face_to_cell.argtypes = [g, _dp, _dp]
+    L.orc_divb_face.argtypes = [g, _dp, C.POINTER(d), C.POINTER(d)]
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_set_threads.restype = C.c_int
     return L
@@ -369,4 +373,18 @@ def divb(grid: Grid, u):
     g = grid.c()
     mx, l1 = C.c_double(), C.c_double()
     lib().orc_divb(C.byref(g), _state(grid, u).reshape(-1), C.byref(mx), C.byref(l1))
+    return mx.value, l1.value
+
+
+def face_to_cell(grid: Grid, u):
+    """Cell-centred state of a staggered (b_face) state, ghosts filled."""
+    out = np.zeros(grid.shape)
+    lib().orc_face_to_cell(C.byref(grid.c()), _state(grid, u).reshape(-1), out.reshape(-1))
+    return out
+
+
+def divb_face(grid: Grid, u):
+    """Face divergence of a staggered (b_face) state: (max, mean) of |div b|."""
+    mx, l1 = C.c_double(), C.c_double()
+    lib().orc_divb_face(C.byref(grid.c()), _state(grid, u).reshape(-1), C.byref(mx), C.byref(l1))
     return mx.value, l1.value

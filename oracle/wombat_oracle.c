@@ -680,6 +680,66 @@ void orc_lf_global(const orc_grid *gr, const double *u, int d, double alpha[7])
     }
 }
 
+/* Staggered storage (the face-B ablation of the CT reading, Sec. 2.1: CT on a
+ * staggered mesh after Ryu et al.): slot B_d of cell i holds the normal field
+ * of its lower d-face, i - 1/2.  The cell-centred field the sweeps see is the
+ * mean of a cell's two faces; an inactive axis has no faces and its component
+ * is used as stored.  The ghosts of u are filled first (the upper face of
+ * the last cell is the first ghost's lower face), and those of uc after. */
+void orc_face_to_cell(const orc_grid *gr, const double *uin, double *uc)
+{
+    geom G = mkgeom(gr);
+    long ntot = 8 * G.sv;
+    double *u = (double *)malloc(sizeof(double) * ntot);
+    int pos[3], v, d;
+    memcpy(u, uin, sizeof(double) * ntot);
+    orc_fill_ghosts(gr, u);
+    memcpy(uc, u, sizeof(double) * ntot);
+    for (pos[2] = 0; pos[2] < G.n[2]; ++pos[2])
+    for (pos[1] = 0; pos[1] < G.n[1]; ++pos[1])
+    for (pos[0] = 0; pos[0] < G.n[0]; ++pos[0]) {
+        long id = cidx(&G, pos[0], pos[1], pos[2]);
+        for (d = 0; d < 3; ++d) {
+            if (!active(&G, d)) continue;
+            int up[3] = { pos[0], pos[1], pos[2] };
+            up[d] += 1;
+            v = BX + d;
+            uc[v * G.sv + id] = 0.5 * (u[v * G.sv + id] + u[v * G.sv + cidx(&G, up[0], up[1], up[2])]);
+        }
+    }
+    orc_fill_ghosts(gr, uc);
+    free(u);
+}
+
+void orc_divb_face(const orc_grid *gr, const double *uin, double *max_abs, double *l1)
+{
+    geom G = mkgeom(gr);
+    long ntot = 8 * G.sv, count = 0;
+    double *u = (double *)malloc(sizeof(double) * ntot);
+    double mx = 0.0, sum = 0.0;
+    int pos[3], d;
+    memcpy(u, uin, sizeof(double) * ntot);
+    orc_fill_ghosts(gr, u);
+    for (pos[2] = 0; pos[2] < G.n[2]; ++pos[2])
+    for (pos[1] = 0; pos[1] < G.n[1]; ++pos[1])
+    for (pos[0] = 0; pos[0] < G.n[0]; ++pos[0]) {
+        long id = cidx(&G, pos[0], pos[1], pos[2]);
+        double div = 0.0;
+        for (d = 0; d < 3; ++d) {
+            if (!active(&G, d)) continue;
+            int up[3] = { pos[0], pos[1], pos[2] };
+            up[d] += 1;
+            div += (u[(BX + d) * G.sv + cidx(&G, up[0], up[1], up[2])] - u[(BX + d) * G.sv + id]) / G.dl[d];
+        }
+        if (fabs(div) > mx) mx = fabs(div);
+        sum += fabs(div);
+        ++count;
+    }
+    *max_abs = mx;
+    *l1 = count ? sum / count : 0.0;
+    free(u);
+}
+
 static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fill, int linear)
 {
     geom G = mkgeom(gr);
@@ -688,6 +748,14 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
     int bad = 0;
     memcpy(u, uin, sizeof(double) * ntot);
     if (fill) orc_fill_ghosts(gr, u);
+    if (gr->b_face) {
+        /* the sweeps see the cell-centred state; the face fields are updated
+         * below from the same edge EMFs */
+        double *uf = (double *)malloc(sizeof(double) * ntot);
+        memcpy(uf, u, sizeof(double) * ntot);
+        orc_face_to_cell(gr, uf, u);
+        free(uf);
+    }
 
     faces FF[3];
     int d, e;
@@ -767,7 +835,9 @@ static int rhs_impl(const orc_grid *gr, const double *uin, double *dudt, int fil
         for (n = 0; n < 3; ++n) {
             int a1 = (n + 1) % 3, a2 = (n + 2) % 3;
             double val;
-            if (active(&G, n))
+            if (active(&G, n) && gr->b_face)
+                val = face_bdot(&G, FF, n, pos[n], pos[a1], pos[a2]);      /* the lower face itself */
+            else if (active(&G, n))
                 val = 0.5 * (face_bdot(&G, FF, n, pos[n], pos[a1], pos[a2])
                            + face_bdot(&G, FF, n, pos[n] + 1, pos[a1], pos[a2]));
             else
@@ -802,11 +872,18 @@ int orc_rhs_linear(const orc_grid *gr, const double *u, double *dudt)
 
 /* dt = C / max over interior cells of sum_d (|v_d| + c_f,d) / dx_d.
  * Returns a negative value if a cell is non-physical. */
-double orc_cfl_dt(const orc_grid *gr, const double *u)
+double orc_cfl_dt(const orc_grid *gr, const double *uin)
 {
     geom G = mkgeom(gr);
     double smax = 0.0;
     int bad = 0, pos[3], d, v;
+    double *ucell = NULL;
+    const double *u = uin;
+    if (gr->b_face) {                 /* wave speeds of the cell-centred field */
+        ucell = (double *)malloc(sizeof(double) * 8 * G.sv);
+        orc_face_to_cell(gr, uin, ucell);
+        u = ucell;
+    }
     for (pos[2] = 0; pos[2] < G.n[2]; ++pos[2])
     for (pos[1] = 0; pos[1] < G.n[1]; ++pos[1])
     for (pos[0] = 0; pos[0] < G.n[0]; ++pos[0]) {
@@ -823,6 +900,7 @@ double orc_cfl_dt(const orc_grid *gr, const double *u)
         }
         if (sum > smax) smax = sum;
     }
+    free(ucell);
     if (bad || !(smax > 0.0)) return -1.0;
     return gr->cfl / smax;
 }

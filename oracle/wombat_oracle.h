@@ -37,6 +37,10 @@ typedef struct {
     int weights;           /* 0: weights of eq. (3); 1: WENO-Z (ablation)      */
     int lf_global;         /* 0: LF speed per stencil; 1: per sweep over the
                               whole box (ablation)                             */
+    int b_face;            /* 0: B slots hold cell-centred B; 1: they hold the
+                              staggered face-normal field, slot B_d of cell i
+                              = b_d at its lower d-face i-1/2 (ablation;
+                              periodic boxes)                                  */
 } orc_grid;
 
 /* ---- scalar WENO5 pieces (Sec. 2.1, eqs. 1-7) ---- */
@@ -101,6 +105,11 @@ int    orc_rk4_step(const orc_grid *g, double *u, double dt);
 int    orc_ssprk3_step(const orc_grid *g, double *u, double dt);
 void   orc_sums(const orc_grid *g, const double *u, double out[8]);
 int    orc_set_threads(int n);      /* OpenMP build: threads in use (serial build: 1) */
+/* Staggered storage (b_face): the cell-centred state of a face-B state (its
+ * ghosts filled), and the face divergence sum_d (b_d(i+1/2) - b_d(i-1/2))/dx_d
+ * over the interior cells (max and mean of its magnitude). */
+void   orc_face_to_cell(const orc_grid *g, const double *u, double *uc);
+void   orc_divb_face(const orc_grid *g, const double *u, double *max_abs, double *l1);
 void   orc_divb(const orc_grid *g, const double *u, double *max_abs,
                 double *l1);
 

@@ -83,7 +83,9 @@ struct wombat_weno {
     int64_t fallbacks;     // routed steps redone with full WENO
     double *lfg;           // global LF speeds: partials, then 7 per direction (WW_LF_GLOBAL only)
     int slab;              // z-slab mode: planes per slab (0: whole box)
+    int fuse;              // the x sweep does the rho, m, E update (3-D, long rows, no slabs, no router)
     void *delay;           // slab mode: the last 3 output planes of a slab (8 vars x 3 planes)
+    void *cellst;          // WW_B_FACE: the cell-centred state the sweeps read
     hipStream_t st;
     int sticky;            // a HIP error happened: every later call fails
     std::string err;
@@ -162,6 +164,7 @@ int ww::validate_config(const wombat_weno_config *c, std::string &why)
         return WW_ERR_INVALID_ARG;
     }
     if (c->slab_planes > 0 && c->nz < 3) { why = "slab_planes needs an active z axis"; return WW_ERR_INVALID_ARG; }
+    if (c->b_storage != WW_B_CELL && c->b_storage != WW_B_FACE) { why = "unknown b_storage"; return WW_ERR_INVALID_ARG; }
     bool user = false;
     for (int f = 0; f < 6; ++f) {
         if (c->bc[f] < 0 || c->bc[f] > 2) { why = "unknown boundary condition"; return WW_ERR_INVALID_ARG; }
@@ -252,6 +255,7 @@ void release(wombat_weno_t *c)
     if (c->qcount) (void)hipFree(c->qcount);
     if (c->lfg) (void)hipFree(c->lfg);
     if (c->delay) (void)hipFree(c->delay);
+    if (c->cellst) (void)hipFree(c->cellst);
     for (int i = 0; i < 2; ++i) if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
 }
 
@@ -346,8 +350,15 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
                const ww::StageCoef &k)
 {
     if (c->slab) return operator_slabs_t<T>(c, us, u0, acc_in, acc_out, out, k);
-    int rc = fill_ghosts_t<T>(c, us);
-    if (rc) return rc;
+    int rc;
+    const bool stag = c->cellst != nullptr;
+    if (stag) {
+        // staggered storage: the sweeps read the cell-centred state (its
+        // ghosts filled); the update advances the face slots of us's layout
+        WW_CHECK(c, ww::launch_face_to_cell<T>(us, (T *)c->cellst, c->G, c->st));
+        us = (T *)c->cellst;
+    }
+    if ((rc = fill_ghosts_t<T>(c, us))) return rc;
     ww::Phys P{ c->cfg.gamma, c->cfg.eps, 1.0 / (c->cfg.gamma - 1.0) };
     if (c->lfg) {
         // global LF speeds of the three sweeps, from this stage's state
@@ -360,7 +371,13 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
         const long tot = c->nsm_blocks[0] + c->nsm_blocks[1] + c->nsm_blocks[2];
         WW_CHECK(c, hipMemsetAsync(c->nsmooth, 0, sizeof(int32_t) * (tot > 0 ? tot : 1), c->st));
     }
-    for (int d = 0; d < 3; ++d) {
+    // with the fused x sweep the sweeps run y, z, x: the x sweep differences
+    // all three directions' rho, m, E fluxes and applies their RK update, and
+    // the update kernel does constrained transport and B only
+    const bool fuse = c->fuse && !c->router;
+    const int order[3] = { fuse ? 1 : 0, fuse ? 2 : 1, fuse ? 0 : 2 };
+    for (int m = 0; m < 3; ++m) {
+        const int d = order[m];
         if (!c->G.act[d]) continue;
         if constexpr (sizeof(T) == 4) {
             if (c->router && c->router_force <= 0) {
@@ -377,10 +394,19 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
             }
         }
         if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
+        if (fuse && d == 0) {
+            const ww::XFuse<T> xf{ u0, acc_in, acc_out, out, (const T *)c->ff[1], (const T *)c->ff[2],
+                                   c->F[1], c->F[2], k };
+            WW_CHECK(c, ww::launch_sweep_x_fused<T>(us, (T *)c->ff[0], c->G, c->F[0], P, c->cfg.weights, xf, c->st));
+            continue;
+        }
         WW_CHECK(c, ww::launch_sweep<T>(d, us, (T *)c->ff[d], c->G, c->F[d], P, c->cfg.weights, c->st));
     }
+    ww::StageCoef kb = k;
+    kb.bonly = fuse ? 1 : 0;
+    kb.stag = stag ? 1 : 0;
     WW_CHECK(c, ww::launch_update<T>(u0, acc_in, acc_out, out, (const T *)c->ff[0],
-                                     (const T *)c->ff[1], (const T *)c->ff[2], c->F, c->G, k,
+                                     (const T *)c->ff[1], (const T *)c->ff[2], c->F, c->G, kb,
                                      c->st));
     return WW_OK;
 }
@@ -388,6 +414,10 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
 template <typename T>
 int cfl_device_t(wombat_weno_t *c, const T *u, double *d_dt, int32_t *d_flag)
 {
+    if (c->cellst) {     // staggered storage: wave speeds of the cell-centred field
+        WW_CHECK(c, ww::launch_face_to_cell<T>(u, (T *)c->cellst, c->G, c->st));
+        u = (const T *)c->cellst;
+    }
     WW_CHECK(c, ww::launch_cfl<T>(u, c->G, c->cfg.gamma, c->cfg.cfl, c->part, c->partflag,
                                   c->nblk, d_dt, d_flag, c->st));
     return WW_OK;
@@ -447,9 +477,45 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[7])
              return (int)WW_OK;
          }, ms[0])))
         return rc;
-    for (int d = 0; d < 3; ++d) {
+    // the update in the forms a step runs: the four RK4 stages (or the three
+    // SSP-RK3 stages), u0 = u, acc and out in the work arrays, dt = 0 so that
+    // repeated launches leave acc and out unchanged; the mean of the forms.
+    // With the fused x sweep, the x sweep is timed in those forms too (the y
+    // and z fluxes it reads are those of u), and the update in its B-only form.
+    const bool fuse = c->fuse && !c->router;
+    const T *fx = (const T *)c->ff[0], *fy = (const T *)c->ff[1], *fz = (const T *)c->ff[2];
+    T *acc = (T *)c->work[c->slab ? 1 : 2], *out = (T *)c->work[0];
+    const bool ssp = c->cfg.integrator == WW_SSPRK3;
+    const int nform = ssp ? 3 : 4;
+    auto form = [&](int s) {
+        ww::StageCoef k = ssp ? ww::StageCoef{ 2, s, 0.0, 0.0, 1.0, s == 0 ? 0.0 : 0.5 }
+                              : ww::StageCoef{ 1, s, 0.0, 0.0 };
+        k.bonly = fuse ? 1 : 0;
+        return k;
+    };
+    auto form_acc_in = [&](int s) {
+        return ssp ? (s == 0 ? (const T *)nullptr : (const T *)c->work[1]) : (const T *)acc;
+    };
+    const int order[3] = { fuse ? 1 : 0, fuse ? 2 : 1, fuse ? 0 : 2 };
+    for (int m = 0; m < 3; ++m) {
+        const int d = order[m];
         if (!c->G.act[d]) continue;
         if (c->lfg) P.ag = c->lfg + ww::LF_PART_DOUBLES + 7 * d;
+        if (fuse && d == 0) {
+            double sum = 0.0;
+            for (int s = 0; s < nform; ++s) {
+                const ww::XFuse<T> xf{ u, form_acc_in(s), acc, out, fy, fz, c->F[1], c->F[2], form(s) };
+                double t = 0.0;
+                if ((rc = time_launches(c, reps, [&] {
+                         return chk(ww::launch_sweep_x_fused<T>(u, (T *)c->ff[0], c->G, c->F[0], P, c->cfg.weights,
+                                                                xf, c->st));
+                     }, t)))
+                    return rc;
+                sum += t;
+            }
+            ms[1] = sum / nform;
+            continue;
+        }
         if ((rc = time_launches(c, reps, [&] {
                  return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
                      return chk(ww::launch_sweep<T>(d, u, (T *)c->ff[d], S, F[d], P, c->cfg.weights, c->st));
@@ -457,18 +523,10 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[7])
              }, ms[1 + d])))
             return rc;
     }
-    // the update in the forms a step runs: the four RK4 stages (or the three
-    // SSP-RK3 stages), u0 = u, acc and out in the work arrays, dt = 0 so that
-    // repeated launches leave acc and out unchanged; the mean of the forms
-    const T *fx = (const T *)c->ff[0], *fy = (const T *)c->ff[1], *fz = (const T *)c->ff[2];
-    T *acc = (T *)c->work[c->slab ? 1 : 2], *out = (T *)c->work[0];
-    const bool ssp = c->cfg.integrator == WW_SSPRK3;
-    const int nform = ssp ? 3 : 4;
     double sum = 0.0;
     for (int s = 0; s < nform; ++s) {
-        ww::StageCoef k = ssp ? ww::StageCoef{ 2, s, 0.0, 0.0, 1.0, s == 0 ? 0.0 : 0.5 }
-                              : ww::StageCoef{ 1, s, 0.0, 0.0 };
-        const T *acc_in = ssp ? (s == 0 ? nullptr : (const T *)c->work[1]) : (const T *)acc;
+        const ww::StageCoef k = form(s);
+        const T *acc_in = form_acc_in(s);
         double t = 0.0;
         if ((rc = time_launches(c, reps, [&] {
                  return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
@@ -486,7 +544,8 @@ int time_kernels_t(wombat_weno_t *c, T *u, int reps, double ms[7])
          }, ms[5])))
         return rc;
     // the update writing L(U) only (wombat_weno_rhs)
-    const ww::StageCoef k0{ 0, 0, 0.0, 0.0 };
+    ww::StageCoef k0{ 0, 0, 0.0, 0.0 };
+    k0.bonly = fuse ? 1 : 0;
     return time_launches(c, reps, [&] {
         return for_slabs(c, [&](const ww::Geom &S, const ww::FaceBox *F) {
             return chk(ww::launch_update<T>(nullptr, nullptr, nullptr, out, fx, fy, fz, F, S, k0, c->st));
@@ -549,6 +608,15 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
             return fail_ctx(nullptr, WW_ERR_UNSUPPORTED,
                             "slab_planes runs the RK4 stages with per-stencil LF speeds, without the router");
     }
+    if (cfg->b_storage == WW_B_FACE) {
+        bool periodic = true;
+        const int n[3] = { cfg->nx, cfg->ny, cfg->nz };
+        for (int d = 0; d < 3; ++d)
+            if (n[d] > 1 && (cfg->bc[2 * d] != WW_BC_PERIODIC || cfg->bc[2 * d + 1] != WW_BC_PERIODIC)) periodic = false;
+        if (!periodic || cfg->slab_planes > 0 || cfg->learned)
+            return fail_ctx(nullptr, WW_ERR_UNSUPPORTED,
+                            "staggered B storage (WW_B_FACE) runs on periodic boxes without slab_planes or the router");
+    }
     wombat_weno_t *c = new (std::nothrow) wombat_weno();
     if (!c) return fail_ctx(nullptr, WW_ERR_OOM, "host allocation failed");
     c->cfg = *cfg;
@@ -558,6 +626,7 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
     c->elems = state_elems(cfg);
     c->st = (hipStream_t)cfg->stream;
     c->nblk = ww::cfl_blocks(c->G);
+    c->fuse = !c->slab && c->G.act[0] && c->G.act[1] && c->G.act[2] && c->F[0].cnt[0] >= ww::sweep_x_fused_min_faces();
     DevGuard dg(cfg->device);
     if (!dg.ok) { delete c; return fail_ctx(nullptr, WW_ERR_HIP, "hipSetDevice failed"); }
     ww::alloc_hook_reset();
@@ -578,6 +647,8 @@ int wombat_weno_init(const wombat_weno_config *cfg, wombat_weno_t **out)
             if (c->G.act[d] && dev_alloc(&c->ff[d], c->esize * ww::NFC * (c->slab ? SF[d].sc : c->F[d].sc)) != hipSuccess)
                 return oom("face fluxes");
     }
+    if (cfg->b_storage == WW_B_FACE && dev_alloc(&c->cellst, c->esize * c->elems) != hipSuccess)
+        return oom("cell-centred state");
     if (c->slab) {
         const size_t db = c->esize * 8 * 3 * c->G.s[2];
         if (dev_alloc(&c->delay, db) != hipSuccess) return oom("slab delay buffer");
@@ -850,7 +921,13 @@ int wombat_weno_divb(wombat_weno_t *ctx, void *d_u, double *max_abs, double *l1)
     if (!d_u || !max_abs || !l1) return fail_ctx(ctx, WW_ERR_INVALID_ARG, "NULL pointer");
     if ((rc = wombat_weno_fill_ghosts(ctx, d_u))) return rc;
     DevGuard dg(ctx->cfg.device);
-    if (ctx->cfg.precision == WW_FP64)
+    if (ctx->cellst && ctx->cfg.precision == WW_FP64)
+        WW_CHECK(ctx, ww::launch_divb_face<double>((const double *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                                   ctx->dsmall + 1, ctx->st));
+    else if (ctx->cellst)
+        WW_CHECK(ctx, ww::launch_divb_face<float>((const float *)d_u, ctx->G, ctx->part, ctx->nblk,
+                                                  ctx->dsmall + 1, ctx->st));
+    else if (ctx->cfg.precision == WW_FP64)
         WW_CHECK(ctx, ww::launch_divb<double>((const double *)d_u, ctx->G, ctx->part, ctx->nblk,
                                               ctx->dsmall + 1, ctx->st));
     else

@@ -9,8 +9,9 @@
 // Global LF speeds (an ablation of the per-stencil speed): per sweep
 // direction and field, the largest |lambda^s| over the sweep's cells.
 // Reductions are two-pass (per-block partials, then one block) with a fixed
-// assignment of cells to threads and a fixed tree: results are bitwise
-// reproducible.  No floating-point atomics.
+// assignment of cells to threads, wavefront butterflies and a fixed order
+// across the waves: results are bitwise reproducible.  No floating-point
+// atomics.
 #include "ww_internal.h"
 
 #include <math.h>
@@ -56,22 +57,62 @@ __global__ __launch_bounds__(256) void ghost_kernel(T *__restrict__ u, Geom G, i
     for (int v = 0; v < 8; ++v) u[di + v * G.sv] = u[si + v * G.sv];
 }
 
+// Reductions: a butterfly over the 64 lanes of each wavefront (__shfl_xor,
+// every lane ends with the wave's result), then the four waves of a block in
+// a fixed order through LDS.  No floating-point atomics: bitwise reproducible.
+constexpr int NW = RB / 64;
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ int wave_isum(int v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Block maximum mx, sums sm and fl (valid in thread 0).
 __device__ __forceinline__ void block_reduce2(double &mx, double &sm, int &fl)
 {
-    __shared__ double smx[RB], ssm[RB];
-    __shared__ int sfl[RB];
-    const int t = threadIdx.x;
-    smx[t] = mx; ssm[t] = sm; sfl[t] = fl;
+    __shared__ double smx[NW], ssm[NW];
+    __shared__ int sfl[NW];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    mx = wave_max(mx);
+    sm = wave_sum(sm);
+    fl = wave_isum(fl);
+    if (l == 0) { smx[w] = mx; ssm[w] = sm; sfl[w] = fl; }
     __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            smx[t] = fmax(smx[t], smx[t + h]);
-            ssm[t] = ssm[t] + ssm[t + h];
-            sfl[t] = sfl[t] + sfl[t + h];
-        }
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NW; ++i) { mx = fmax(mx, smx[i]); sm += ssm[i]; fl += sfl[i]; }
     }
-    mx = smx[0]; sm = ssm[0]; fl = sfl[0];
+}
+
+// Block reduction of K values per thread (sum or max; valid in thread 0).
+template <int K, bool MAX>
+__device__ __forceinline__ void block_reduce_k(double (&v)[K])
+{
+    __shared__ double sv[K][NW];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = MAX ? wave_max(v[k]) : wave_sum(v[k]);
+        if (l == 0) sv[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            for (int i = 1; i < NW; ++i) v[k] = MAX ? fmax(v[k], sv[k][i]) : v[k] + sv[k][i];
 }
 
 __device__ __forceinline__ void cell_pos(const Geom &G, long c, int (&p)[3])
@@ -170,31 +211,19 @@ __global__ __launch_bounds__(RB) void lf_partial(const T *__restrict__ u, Geom G
         const double lam[7] = { vn - cf, vn - ca, vn - cs, vn, vn + cs, vn + ca, vn + cf };
         for (int k = 0; k < 7; ++k) m[k] = fmax(m[k], fabs(lam[k]));
     }
-    __shared__ double sm[7][RB];
-    for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = m[k];
-    __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x < 7) part[7 * blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+    block_reduce_k<7, true>(m);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; ++k) part[7 * blockIdx.x + k] = m[k];
 }
 
 __global__ __launch_bounds__(RB) void lf_final(const double *part, int nblk, double *out)
 {
-    __shared__ double sm[7][RB];
     double m[7] = { 0, 0, 0, 0, 0, 0, 0 };
     for (int b = threadIdx.x; b < nblk; b += RB)
         for (int k = 0; k < 7; ++k) m[k] = fmax(m[k], part[7 * b + k]);
-    for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = m[k];
-    __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            for (int k = 0; k < 7; ++k) sm[k][threadIdx.x] = fmax(sm[k][threadIdx.x], sm[k][threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x < 7) out[threadIdx.x] = sm[threadIdx.x][0];
+    block_reduce_k<7, true>(m);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; ++k) out[k] = m[k];
 }
 
 template <typename T>
@@ -208,31 +237,19 @@ __global__ __launch_bounds__(RB) void sums_partial(const T *__restrict__ u, Geom
         const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
         for (int v = 0; v < 8; ++v) acc[v] += (double)u[id + v * G.sv];
     }
-    __shared__ double s[8][RB];
-    for (int v = 0; v < 8; ++v) s[v][threadIdx.x] = acc[v];
-    __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            for (int v = 0; v < 8; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) part[blockIdx.x * 8 + threadIdx.x] = s[threadIdx.x][0];
+    block_reduce_k<8, false>(acc);
+    if (threadIdx.x == 0)
+        for (int v = 0; v < 8; ++v) part[blockIdx.x * 8 + v] = acc[v];
 }
 
 __global__ __launch_bounds__(RB) void sums_final(const double *part, int nblk, double *out)
 {
-    __shared__ double s[8][RB];
     double acc[8] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     for (int b = threadIdx.x; b < nblk; b += RB)
         for (int v = 0; v < 8; ++v) acc[v] += part[b * 8 + v];
-    for (int v = 0; v < 8; ++v) s[v][threadIdx.x] = acc[v];
-    __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            for (int v = 0; v < 8; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) out[threadIdx.x] = s[threadIdx.x][0];
+    block_reduce_k<8, false>(acc);
+    if (threadIdx.x == 0)
+        for (int v = 0; v < 8; ++v) out[v] = acc[v];
 }
 
 // Corner divergence at corners i+1/2 (i = 0..n-1) on active axes.
@@ -278,6 +295,53 @@ __global__ __launch_bounds__(RB) void divb_final(const double *part, int nblk, d
     for (int b = threadIdx.x; b < nblk; b += RB) { mx = fmax(mx, part[2 * b]); sm += part[2 * b + 1]; }
     block_reduce2(mx, sm, dummy);
     if (threadIdx.x == 0) { out[0] = mx; out[1] = sm / ncell; }
+}
+
+// Staggered storage (periodic boxes): cell-centred state of the interior cells.
+template <typename T>
+__global__ __launch_bounds__(RB) void face_to_cell_kernel(const T *__restrict__ u, T *__restrict__ uc, Geom G)
+{
+    const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+    const long c = (long)blockIdx.x * RB + threadIdx.x;
+    if (c >= ncell) return;
+    int p[3];
+    cell_pos(G, c, p);
+    const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int d = v - 4;
+        // the upper face of the last cell is the periodic image of face 0
+        if (d >= 0 && d < 3 && G.act[d])
+            uc[id + v * G.sv] = T(0.5) * (u[id + v * G.sv]
+                                          + u[id + (p[d] + 1 < G.n[d] ? G.s[d] : -(long)(G.n[d] - 1) * G.s[d])
+                                              + v * G.sv]);
+        else
+            uc[id + v * G.sv] = u[id + v * G.sv];
+    }
+}
+
+// Face divergence of a staggered state (periodic box).
+template <typename T>
+__global__ __launch_bounds__(RB) void divb_face_partial(const T *__restrict__ u, Geom G, double *part)
+{
+    const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+    double mx = 0.0, sm = 0.0;
+    int dummy = 0;
+    for (long c = (long)blockIdx.x * RB + threadIdx.x; c < ncell; c += (long)gridDim.x * RB) {
+        int p[3];
+        cell_pos(G, c, p);
+        const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
+        double div = 0.0;
+        for (int d = 0; d < 3; ++d)
+            if (G.act[d]) {
+                const long up = p[d] + 1 < G.n[d] ? G.s[d] : -(long)(G.n[d] - 1) * G.s[d];   // periodic
+                div += ((double)u[id + up + (4 + d) * G.sv] - (double)u[id + (4 + d) * G.sv]) * G.idl[d];
+            }
+        mx = fmax(mx, fabs(div));
+        sm += fabs(div);
+    }
+    block_reduce2(mx, sm, dummy);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = mx; part[2 * blockIdx.x + 1] = sm; }
 }
 
 }  // namespace
@@ -386,6 +450,25 @@ hipError_t launch_divb(const T *u, const Geom &G, double *part, int nblk, double
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_face_to_cell(const T *u, T *uc, const Geom &G, hipStream_t st)
+{
+    const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+    hipLaunchKernelGGL((face_to_cell_kernel<T>), dim3((unsigned)((ncell + RB - 1) / RB)), dim3(RB), 0, st, u, uc, G);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_divb_face(const T *u, const Geom &G, double *part, int nblk, double *d_out, hipStream_t st)
+{
+    hipLaunchKernelGGL((divb_face_partial<T>), dim3(nblk), dim3(RB), 0, st, u, G, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double ncell = (double)G.n[0] * G.n[1] * G.n[2];
+    hipLaunchKernelGGL(divb_final, dim3(1), dim3(RB), 0, st, part, nblk, ncell, d_out);
+    return hipGetLastError();
+}
+
 #define WW_INST(T)                                                                           \
     template hipError_t launch_ghosts<T>(T *, const Geom &, int, const int *, hipStream_t);  \
     template hipError_t launch_cfl<T>(const T *, const Geom &, double, double, double *,      \
@@ -395,7 +478,10 @@ hipError_t launch_divb(const T *u, const Geom &G, double *part, int nblk, double
     template hipError_t launch_divb<T>(const T *, const Geom &, double *, int, double *,      \
                                        hipStream_t);                                         \
     template hipError_t launch_lf_global<T>(const T *, const Geom &, int, double, double *,   \
-                                            double *, hipStream_t);
+                                            double *, hipStream_t);                          \
+    template hipError_t launch_face_to_cell<T>(const T *, T *, const Geom &, hipStream_t);    \
+    template hipError_t launch_divb_face<T>(const T *, const Geom &, double *, int, double *, \
+                                            hipStream_t);
 WW_INST(double)
 WW_INST(float)
 

@@ -10,8 +10,9 @@
 // each of its patches through the full stage: (stage 0 only) the patch's CFL
 // time step (0, and the patch left unadvanced, if any cell is non-physical),
 // periodic ghost fill, x/y/z characteristic WENO sweeps into the
-// block's own face-flux scratch, then flux differences, CT and the RK update
-// -- the same device functions as the single-box kernels.
+// block's own face-flux scratch (y and z first; the flattened x tiles also
+// apply the rho, m, E update), then CT and the B part of the RK update -- the
+// same device functions as the single-box kernels.
 #include "ww_batch.h"
 #include "ww_sweep_dev.h"
 #include "ww_update_dev.h"
@@ -60,8 +61,8 @@ template <typename T>
 __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G, double gamma,
                                          double cfl, double *dt_out, int32_t *flag_out)
 {
-    __shared__ double smx[RB];
-    __shared__ int sfl[RB];
+    __shared__ double smx[sw::ROWS];
+    __shared__ int sfl[sw::ROWS];
     const int tid = threadIdx.x + sw::TILE * threadIdx.y;
     const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
     double mx = 0.0;
@@ -93,17 +94,19 @@ __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G,
         }
         mx = fmax(mx, s);
     }
-    smx[tid] = mx;
-    sfl[tid] = bad;
-    __syncthreads();
-    for (int h = RB / 2; h > 0; h >>= 1) {
-        if (tid < h) { smx[tid] = fmax(smx[tid], smx[tid + h]); sfl[tid] += sfl[tid + h]; }
-        __syncthreads();
+    // butterfly over the wave's 64 lanes, then the four waves in order
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, m));
+        bad += __shfl_xor(bad, m);
     }
+    if (threadIdx.x == 0) { smx[threadIdx.y] = mx; sfl[threadIdx.y] = bad; }
+    __syncthreads();
     if (tid == 0) {
-        const bool ok = smx[0] > 0.0 && sfl[0] == 0;
-        *dt_out = ok ? cfl / smx[0] : 0.0;
-        *flag_out = sfl[0] > 0 ? sfl[0] : (ok ? 0 : 1);
+        for (int w = 1; w < sw::ROWS; ++w) { mx = fmax(mx, smx[w]); bad += sfl[w]; }
+        const bool ok = mx > 0.0 && bad == 0;
+        *dt_out = ok ? cfl / mx : 0.0;
+        *flag_out = bad > 0 ? bad : (ok ? 0 : 1);
     }
     __syncthreads();
 }
@@ -114,6 +117,7 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
     constexpr int C0 = sw::tile_cells<0, FT>(), C1 = sw::tile_cells<1, FT>();
     constexpr int CMAX = (C0 > C1 ? C0 : C1) > sw::XF_MAXC ? (C0 > C1 ? C0 : C1) : sw::XF_MAXC;
     __shared__ T sq[sw::NQ * CMAX];
+    __shared__ T hx[5 * sw::XF_FACES];     // rho, m, E fluxes of the fused x tile
     __shared__ double sdt;
     const int b = blockIdx.x;
     T *ff = a.scratch + (long)b * a.slot_elems;
@@ -138,17 +142,15 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
         if (dtp == 0.0) continue;        // non-physical patch: left unadvanced
         ghost_fill_patch<T>(us, G);
         T *fx = ff, *fy = ff + NFC * D.F[0].sc, *fz = fy + NFC * D.F[1].sc;
-        // x sweep
-        if (D.xflat) {
-            const long nt = ((long)D.F[0].cnt[0] * D.F[0].cnt[1] * D.F[0].cnt[2] + sw::XF_FACES - 1)
-                            / sw::XF_FACES;
-            for (long t = 0; t < nt; ++t) sw::sweep_tile_xflat<T>(us, fx, G, D.F[0], P, t, sq);
-        } else {
-            long na, nb;
-            sw::sweep_tiles<0, FT>(D.F[0], na, nb);
-            for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T>(us, fx, G, D.F[0], P, ta, tb, sq);
-        }
+        // the RK stage of this patch, with its own dt
+        StageCoef kc;
+        kc.mode = 1;
+        kc.s = a.s;
+        kc.bdt = a.bw * dtp;
+        kc.cdt = a.cw * dtp;
+        // y and z sweeps, then the x sweep: on the flattened x tiles it also
+        // differences every direction's rho, m, E fluxes and applies their RK
+        // update, and the update below is left with constrained transport
         {
             long na, nb;
             sw::sweep_tiles<1, FT>(D.F[1], na, nb);
@@ -158,7 +160,20 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
             for (long tb = 0; tb < nb; ++tb)
                 for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T>(us, fz, G, D.F[2], P, ta, tb, sq);
         }
-        // flux differences, CT, RK with the patch's own dt
+        const bool fused = D.xflat != 0;
+        if (fused) {
+            const XFuse<T> xf{ a.u0 + D.soff, a.acc + D.soff, a.acc + D.soff, a.out + D.soff, fy, fz, D.F[1], D.F[2],
+                               kc };
+            const long total = (long)D.F[0].cnt[0] * D.F[0].cnt[1] * D.F[0].cnt[2];
+            const long nt = (total - 1 + sw::XF_FACES - 2) / (sw::XF_FACES - 1);
+            for (long t = 0; t < nt; ++t) sw::sweep_tile_xflat_fused<T>(us, fx, G, D.F[0], P, t, sq, hx, xf);
+        } else {
+            long na, nb;
+            sw::sweep_tiles<0, FT>(D.F[0], na, nb);
+            for (long tb = 0; tb < nb; ++tb)
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T>(us, fx, G, D.F[0], P, ta, tb, sq);
+        }
+        // flux differences (B only after the fused x sweep), CT, RK
         up::UpdArgs<T> ua;
         ua.u0 = a.u0 + D.soff;
         ua.acc_in = a.acc + D.soff;
@@ -169,10 +184,8 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
         ua.G = G;
         ua.odelta = 0;
         ua.osv = G.sv;
-        ua.c.mode = 1;
-        ua.c.s = a.s;
-        ua.c.bdt = a.bw * dtp;
-        ua.c.cdt = a.cw * dtp;
+        ua.c = kc;
+        ua.c.bonly = fused ? 1 : 0;
         // one thread per cell (marching columns in k cost more registers and
         // left whole passes of a small patch's columns half idle: measured
         // 1.5x slower here)

@@ -311,6 +311,8 @@ int wombat_weno_batch_init(const wombat_weno_config *cfg, int npatch, const int3
         return bfail(nullptr, WW_ERR_UNSUPPORTED, "the batched form uses the RK4 step only");
     if (cfg->lf_speed != WW_LF_LOCAL)
         return bfail(nullptr, WW_ERR_UNSUPPORTED, "the batched form uses the per-stencil LF speeds only");
+    if (cfg->b_storage != WW_B_CELL)
+        return bfail(nullptr, WW_ERR_UNSUPPORTED, "the batched form stores cell-centred B only");
     for (int p = 0; p < npatch; ++p)
         for (int d = 0; d < 3; ++d)
             if (dims[3 * p + d] < 4 || dims[3 * p + d] > 1024)

@@ -78,6 +78,9 @@ struct StageCoef {
     double cdt;        // weight of L in out
     double a0 = 0.0;   // mode 2: weight of u0
     double a1 = 0.0;   // mode 2: weight of us
+    int bonly = 0;     // update B only (CT): rho, m, E were updated by the fused x sweep
+    int stag = 0;      // staggered storage: B slot d of a cell is its lower d-face's field,
+                       // advanced by that face's update (not the mean of two faces)
 };
 // odelta, osv: out[v] of the cell at state index id is written at
 // out[id + odelta + v * osv] (defaults: the layout of the other arrays).
@@ -85,6 +88,28 @@ template <typename T>
 hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const T *fx,
                          const T *fy, const T *fz, const FaceBox *F, const Geom &G,
                          const StageCoef &c, hipStream_t st, long odelta = 0, long osv = 0);
+
+// The x sweep with the rho, m, E part of the update fused in (3 active axes,
+// rows of at least sweep_x_fused_min_faces() faces): per interior cell, the
+// x flux difference from the sweep's own face fluxes, the y and z flux
+// differences from the face fluxes of those sweeps (fy, fz in their boxes),
+// in the order x, y, z, then the RK combination of the stage for those five
+// variables.  Only the transverse-B components (slots 4, 5) of the x fluxes
+// are stored; the update then runs with StageCoef::bonly.
+template <typename T>
+struct XFuse {
+    const T *u0;
+    const T *acc_in;
+    T *acc_out;
+    T *out;
+    const T *fy, *fz;
+    FaceBox by, bz;
+    StageCoef c;
+};
+template <typename T>
+hipError_t launch_sweep_x_fused(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
+                                int weights, const XFuse<T> &xf, hipStream_t st);
+int sweep_x_fused_min_faces();
 
 template <typename T>
 hipError_t launch_ghosts(T *u, const Geom &G, int axis, const int bc[6], hipStream_t st);
@@ -110,6 +135,16 @@ hipError_t launch_lf_global(const T *u, const Geom &G, int d, double gamma, doub
 template <typename T>
 hipError_t launch_sums(const T *u, const Geom &G, double *part, int nblk, double *d_out,
                        hipStream_t st);
+
+// Staggered storage (periodic boxes): the cell-centred state uc of u
+// (interior; B_d the mean of a cell's two d-faces on an active axis, the
+// slot itself on an inactive one), and the face divergence
+// sum_d (b_d(i+1/2) - b_d(i-1/2))/dx_d of u (max, mean of |.|) into d_out[0..1].
+template <typename T>
+hipError_t launch_face_to_cell(const T *u, T *uc, const Geom &G, hipStream_t st);
+template <typename T>
+hipError_t launch_divb_face(const T *u, const Geom &G, double *part, int nblk, double *d_out,
+                            hipStream_t st);
 int sums_blocks(const Geom &G);
 
 template <typename T>

@@ -104,7 +104,8 @@ int wombat_weno_rhs_noalloc(const wombat_weno_config *cfg, void *d_u, void *d_du
     if (!d_u || !d_dudt) return fail(WW_ERR_INVALID_ARG, "NULL pointer");
     if (d_u == d_dudt) return fail(WW_ERR_INVALID_ARG, "d_dudt must not alias d_u");
     if (cfg->learned) return fail(WW_ERR_UNSUPPORTED, "the learned router needs a context");
-    if (cfg->slab_planes != 0) return fail(WW_ERR_UNSUPPORTED, "slab_planes needs a context");
+    if (cfg->b_storage != WW_B_CELL || cfg->slab_planes != 0)
+        return fail(WW_ERR_UNSUPPORTED, "staggered B storage and slab_planes need a context");
     if (cfg->device >= MAX_DEVICES) return fail(WW_ERR_UNSUPPORTED, "device ordinal beyond 63");
     ww::Geom G;
     ww::FaceBox F[3];

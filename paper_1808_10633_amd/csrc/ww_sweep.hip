@@ -28,6 +28,36 @@ __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xseg_kernel(const T *_
     sw::sweep_tile_xseg<T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, sq);
 }
 
+// Hardware block b runs on XCD b % 8 (blocks are dealt round-robin to the
+// eight XCDs, each with its own L2).  The fused x sweep renumbers them so
+// that each XCD walks a contiguous range of tiles: neighbouring rows, whose
+// cells read the same y faces, then meet in one L2.
+constexpr int NXCD = 8;
+
+template <typename T, bool WZ, bool GLF>
+__global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xfused_kernel(const T *__restrict__ u,
+                                                           T *__restrict__ flux, Geom G, FaceBox F, Phys P,
+                                                           XFuse<T> xf, long ntile, long per_xcd)
+{
+    __shared__ T sq[sw::NQ * sw::ROWS * sw::NCX];
+    __shared__ T hx[5 * sw::TILE * sw::ROWS];
+    const long tile = (long)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+    if (tile >= ntile) return;
+    sw::sweep_tile_xseg_fused<T, WZ, GLF>(u, flux, G, F, P, tile, sq, hx, xf);
+}
+
+template <typename T, bool WZ, bool GLF>
+hipError_t launch_xfused(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P, const XFuse<T> &xf,
+                         hipStream_t st)
+{
+    const long total = (long)F.cnt[0] * F.cnt[1] * F.cnt[2];
+    const long nt = (total - 1 + sw::XFUSE_STRIDE - 1) / sw::XFUSE_STRIDE;
+    const long per = (nt + NXCD - 1) / NXCD;
+    hipLaunchKernelGGL((sweep_xfused_kernel<T, WZ, GLF>), dim3((unsigned)(per * NXCD)), dim3(sw::TILE, sw::ROWS), 0,
+                       st, u, flux, G, F, P, xf, nt, per);
+    return hipGetLastError();
+}
+
 // FP64 y/z sweeps: 32 positions x 8 faces per tile (1.6 staged cells per
 // face instead of 2.25 with 64 x 4, in 43 KB of LDS); measured 3 % faster at
 // 512^3.  FP32 keeps 64 positions x 8 faces (sweep_tile, FT = 8).
@@ -95,6 +125,25 @@ hipError_t launch_sweep(int dir, const T *u, T *flux, const Geom &G, const FaceB
     if (glf) return launch_dirs<T, false, true>(dir, u, flux, G, F, P, st);
     return launch_dirs<T, false, false>(dir, u, flux, G, F, P, st);
 }
+
+int sweep_x_fused_min_faces() { return sw::XSEG_MIN; }
+
+template <typename T>
+hipError_t launch_sweep_x_fused(const T *u, T *flux, const Geom &G, const FaceBox &F, const Phys &P,
+                                int weights, const XFuse<T> &xf, hipStream_t st)
+{
+    if (F.cnt[0] < sw::XSEG_MIN || !(G.act[0] && G.act[1] && G.act[2])) return hipErrorInvalidValue;
+    const bool z = weights == WEIGHTS_Z, glf = P.ag != nullptr;
+    if (z && glf) return launch_xfused<T, true, true>(u, flux, G, F, P, xf, st);
+    if (z) return launch_xfused<T, true, false>(u, flux, G, F, P, xf, st);
+    if (glf) return launch_xfused<T, false, true>(u, flux, G, F, P, xf, st);
+    return launch_xfused<T, false, false>(u, flux, G, F, P, xf, st);
+}
+
+template hipError_t launch_sweep_x_fused<double>(const double *, double *, const Geom &, const FaceBox &,
+                                                 const Phys &, int, const XFuse<double> &, hipStream_t);
+template hipError_t launch_sweep_x_fused<float>(const float *, float *, const Geom &, const FaceBox &,
+                                                const Phys &, int, const XFuse<float> &, hipStream_t);
 
 template hipError_t launch_sweep<double>(int, const double *, double *, const Geom &,
                                          const FaceBox &, const Phys &, int, hipStream_t);

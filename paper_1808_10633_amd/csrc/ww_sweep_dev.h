@@ -30,6 +30,7 @@
 // The sweep axis is a template parameter: no data is transposed.
 #pragma once
 #include "ww_internal.h"
+#include "ww_update_dev.h"
 
 #include <math.h>
 
@@ -554,6 +555,73 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
     __syncthreads();
 }
 
+// The rho, m, E update of one cell in the fused x sweeps, in two parts:
+// fused_cell_load issues the cell's global loads (its y and z faces' fluxes
+// and the RK arrays the stage form reads) before the tile's barrier, so that
+// they are in flight while the other waves finish their face fluxes;
+// fused_cell_store forms L from the two x faces in LDS and the loaded
+// values (the update kernel's expressions and order: x, y, z) and stores
+// the RK combination (rk_store_vars's expressions: identical results).
+template <typename T>
+struct FusedCell {
+    T fyl[5], fyr[5], fzl[5], fzr[5], w0[5], w1[5];
+    long id;
+};
+
+template <typename T>
+__device__ __forceinline__ void fused_cell_load(const XFuse<T> &xf, const Geom &G, int i, int j, int k,
+                                                FusedCell<T> &c)
+{
+    const int hs[5] = { 0, 1, 2, 3, 6 }, hv[5] = { 0, 1, 2, 3, 7 };
+    c.id = G.base + i * G.s[0] + j * G.s[1] + (long)k * G.s[2];
+    const long yl = xf.by.idx(i, j, k), yr = xf.by.idx(i, j + 1, k);
+    const long zl = xf.bz.idx(i, j, k), zr = xf.bz.idx(i, j, k + 1);
+    const StageCoef &q = xf.c;
+    const bool u0 = (q.mode == 1 && q.s < 3) || q.mode == 2;
+    const bool ac = (q.mode == 1 && q.s > 0) || (q.mode == 2 && q.a1 != 0.0);
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        c.fyl[h] = xf.fy[hs[h] * xf.by.sc + yl];
+        c.fyr[h] = xf.fy[hs[h] * xf.by.sc + yr];
+        c.fzl[h] = xf.fz[hs[h] * xf.bz.sc + zl];
+        c.fzr[h] = xf.fz[hs[h] * xf.bz.sc + zr];
+        c.w0[h] = u0 ? xf.u0[c.id + hv[h] * G.sv] : T(0);
+        c.w1[h] = ac ? xf.acc_in[c.id + hv[h] * G.sv] : T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom &G, const T *hx, int nh, int tid,
+                                                 const FusedCell<T> &c)
+{
+    const int hv[5] = { 0, 1, 2, 3, 7 };
+    const T idx = T(G.idl[0]), idy = T(G.idl[1]), idz = T(G.idl[2]);
+    const StageCoef &q = xf.c;
+    const T bdt = T(q.bdt), cdt = T(q.cdt), a0 = T(q.a0), a1 = T(q.a1);
+    const long sv = G.sv, id = c.id;
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        T L = T(0);
+        L -= (hx[h * nh + tid + 1] - hx[h * nh + tid]) * idx;
+        L -= (c.fyr[h] - c.fyl[h]) * idy;
+        L -= (c.fzr[h] - c.fzl[h]) * idz;
+        const long o = id + hv[h] * sv;
+        if (q.mode == 0) {
+            xf.out[o] = L;
+        } else if (q.mode == 2) {
+            xf.out[o] = q.a1 != 0.0 ? a0 * c.w0[h] + a1 * c.w1[h] + cdt * L : a0 * c.w0[h] + cdt * L;
+        } else if (q.s == 0) {
+            xf.acc_out[o] = c.w0[h] + bdt * L;
+            xf.out[o] = c.w0[h] + cdt * L;
+        } else if (q.s < 3) {
+            xf.acc_out[o] = c.w1[h] + bdt * L;
+            xf.out[o] = c.w0[h] + cdt * L;
+        } else {
+            xf.out[o] = c.w1[h] + cdt * L;
+        }
+    }
+}
+
 // x sweep for short rows (batched patches): the block takes XF_FACES
 // consecutive faces of the flattened (row, face) space, stages every cell of
 // the rows they touch (-3..n+2), and each thread computes one face.  The
@@ -568,21 +636,20 @@ __host__ __device__ inline int xflat_cells(int nx, long nrows)
     return (int)(span * (nx + 6));
 }
 
+// Stage every cell of the rows that faces g0 .. g0+XF_FACES-1 touch; returns
+// the first row (sq with stride XF_MAXC).
 template <typename T>
-__device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__restrict__ flux,
-                                                 const Geom &G, const FaceBox &F, const Phys &P,
-                                                 long tile, T *sq)
+__device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F, const Phys &P,
+                                            long g0, T *sq)
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
     const int nf = F.cnt[0], rowc = G.n[0] + 6;
     const long nrows = (long)F.cnt[1] * F.cnt[2];
-    const long g0 = tile * XF_FACES;
     const long r_lo = g0 / nf;
     long r_hi = (g0 + XF_FACES - 1) / nf;
     if (r_hi > nrows - 1) r_hi = nrows - 1;
     const int ncell = (int)(r_hi - r_lo + 1) * rowc;
     const int tid = threadIdx.x + TILE * threadIdx.y;
-    stage_begin();
     for (int c = tid; c < ncell; c += XF_FACES) {
         long row = r_lo + c / rowc;
         int x = c % rowc - 3;
@@ -590,6 +657,20 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
         long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
         stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XF_MAXC);
     }
+    return r_lo;
+}
+
+template <typename T>
+__device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__restrict__ flux,
+                                                 const Geom &G, const FaceBox &F, const Phys &P,
+                                                 long tile, T *sq)
+{
+    const int nf = F.cnt[0], rowc = G.n[0] + 6;
+    const long nrows = (long)F.cnt[1] * F.cnt[2];
+    const long g0 = tile * XF_FACES;
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    stage_begin();
+    const long r_lo = xflat_stage(u, G, F, P, g0, sq);
     __syncthreads();
     stage_end();
     const long g = g0 + tid;
@@ -605,6 +686,60 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
         face_flux<T>(sq, XF_MAXC, (int)(row - r_lo) * rowc + f, 1, P.gamma, P.igm1, (T)P.eps, out);
         store_face<0, T>(flux, F, pos, out);
     }
+    __syncthreads();
+}
+
+// The flattened x sweep with the rho, m, E part of the update fused in (the
+// batched form's counterpart of sweep_tile_xseg_fused): tiles of XF_FACES
+// faces overlapping by one (tile t starts at face (XF_FACES-1) t), the
+// fluxes' rho, m, E in LDS (hx, 5 x XF_FACES), and thread tid takes the cell
+// between faces tid and tid+1 of one row when the row is interior: x, y, z
+// differences in the update kernel's order and expressions, then the RK
+// combination.  Only the transverse-B fluxes of the x faces are stored.
+// Ends with a block barrier.
+template <typename T>
+__device__ __forceinline__ void sweep_tile_xflat_fused(const T *__restrict__ u, T *__restrict__ flux,
+                                                       const Geom &G, const FaceBox &F, const Phys &P,
+                                                       long tile, T *sq, T *hx, const XFuse<T> &xf)
+{
+    constexpr int STRIDE = XF_FACES - 1;
+    const int nf = F.cnt[0], rowc = G.n[0] + 6;
+    const long total = (long)F.cnt[1] * F.cnt[2] * nf;
+    const long g0 = tile * STRIDE;
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    stage_begin();
+    const long r_lo = xflat_stage(u, G, F, P, g0, sq);
+    __syncthreads();
+    stage_end();
+    const long g = g0 + tid;
+    const bool valid = g < total;
+    int pos[3] = { 0, 0, 0 };
+    if (valid) {
+        const long row = g / nf;
+        const int f = (int)(g - row * nf);
+        pos[0] = f;
+        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
+        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
+        T out[7];
+        face_flux<T>(sq, XF_MAXC, (int)(row - r_lo) * rowc + f, 1, P.gamma, P.igm1, (T)P.eps, out);
+        hx[0 * XF_FACES + tid] = out[0];
+        hx[1 * XF_FACES + tid] = out[1];
+        hx[2 * XF_FACES + tid] = out[2];
+        hx[3 * XF_FACES + tid] = out[3];
+        hx[4 * XF_FACES + tid] = out[6];
+        if (tid < STRIDE || g == total - 1) {
+            const long fi = F.idx(pos[0], pos[1], pos[2]);
+            flux[4 * F.sc + fi] = out[4];
+            flux[5 * F.sc + fi] = out[5];
+        }
+    }
+    const int i = pos[0], j = pos[1], k = pos[2];
+    const bool cell = valid && tid < STRIDE && g + 1 < total && i + 1 < nf && j >= 0 && j < G.n[1] && k >= 0 &&
+                      k < G.n[2];
+    FusedCell<T> fc;
+    if (cell) fused_cell_load<T>(xf, G, i, j, k, fc);
+    __syncthreads();
+    if (cell) fused_cell_store<T>(xf, G, hx, XF_FACES, tid, fc);
     __syncthreads();
 }
 
@@ -633,13 +768,15 @@ struct XSeg {
     __device__ int k(int s) const { return s == 0 ? k0 : s == 1 ? k1 : s == 2 ? k2 : k3; }
 };
 
-__device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile)
+// stride: first face of tile t is t * stride (TILE*ROWS, or TILE*ROWS - 1 for
+// tiles that overlap by one face).
+__device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile, int stride = TILE * ROWS)
 {
     constexpr int TF = TILE * ROWS;
     XSeg X;
     X.nf = F.cnt[0];
     const long total = (long)F.cnt[1] * F.cnt[2] * X.nf;
-    X.g0 = tile * TF;
+    X.g0 = tile * stride;
     const long g1 = (X.g0 + TF - 1 < total - 1) ? X.g0 + TF - 1 : total - 1;
     X.nface = (int)(g1 - X.g0 + 1);
     const long r_lo = X.g0 / X.nf;
@@ -712,6 +849,58 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
                                                          nullptr, P.ag);
         store_face<0, T>(flux, F, pos, out);
     }
+}
+
+// The x sweep with the hydro part of the update fused in.  Tiles of 256
+// faces overlap by one (tile t starts at face 255 t of the row-major face
+// sequence), so both faces of every cell of a row meet in one tile.  After
+// the fluxes, each thread puts its face's rho, m, E fluxes in LDS (hx, 5 x
+// 256), and thread tid takes the cell between faces tid and tid+1 when both
+// lie in one row and the row is interior: its x difference from LDS, its y
+// and z differences from the other sweeps' face fluxes (same expressions
+// and order as the update kernel: the results are identical), then the RK
+// combination of rho, m, E.  Only the transverse-B fluxes (slots 4, 5) are
+// stored, once per face (the overlapping face by the next tile).
+constexpr int XFUSE_STRIDE = TILE * ROWS - 1;
+
+template <typename T, bool WZ = false, bool GLF = false>
+__device__ __forceinline__ void sweep_tile_xseg_fused(const T *__restrict__ u, T *__restrict__ flux,
+                                                      const Geom &G, const FaceBox &F, const Phys &P,
+                                                      long tile, T *sq, T *hx, const XFuse<T> &xf)
+{
+    stage_begin();
+    const XSeg X = xseg_setup(F, tile, XFUSE_STRIDE);
+    xseg_stage<T>(u, G, F, P, X, sq);
+    __syncthreads();
+    stage_end();
+    const int tid = threadIdx.x + TILE * threadIdx.y;
+    constexpr int NH = TILE * ROWS;
+    int pos[3], off;
+    const bool valid = xseg_face(F, X, tid, pos, off);
+    if (valid) {
+        T out[7];
+        face_flux<T, false, WZ, GLF, (sizeof(T) == 4)>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out,
+                                                         nullptr, P.ag);
+        hx[0 * NH + tid] = out[0];
+        hx[1 * NH + tid] = out[1];
+        hx[2 * NH + tid] = out[2];
+        hx[3 * NH + tid] = out[3];
+        hx[4 * NH + tid] = out[6];
+        const long total = (long)F.cnt[1] * F.cnt[2] * F.cnt[0];
+        if (tid < XFUSE_STRIDE || X.g0 + tid == total - 1) {
+            const long fi = F.idx(pos[0], pos[1], pos[2]);
+            flux[4 * F.sc + fi] = out[4];
+            flux[5 * F.sc + fi] = out[5];
+        }
+    }
+    // the cell between faces tid and tid + 1 of one row (face f sits at f - 1/2)
+    const int i = pos[0], j = pos[1], k = pos[2];
+    const bool cell = valid && tid < XFUSE_STRIDE && tid + 1 < X.nface && i + 1 < F.cnt[0] && j >= 0 &&
+                      j < G.n[1] && k >= 0 && k < G.n[2];
+    FusedCell<T> fc;
+    if (cell) fused_cell_load<T>(xf, G, i, j, k, fc);
+    __syncthreads();
+    if (cell) fused_cell_store<T>(xf, G, hx, NH, tid, fc);
 }
 
 // y or z sweep with PW positions of the transverse plane (x fastest) per

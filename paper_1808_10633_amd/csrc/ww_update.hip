@@ -29,7 +29,7 @@ constexpr int NXCD = 8;                              // MI355X: 8 XCDs, blocks d
 // marching in k (up::march_column).  Hardware block b runs on XCD b % 8;
 // blocks are renumbered so that each XCD owns a contiguous range of tiles
 // (neighbouring rows share its L2).
-template <typename T>
+template <typename T, bool BONLY, bool STAG>
 __global__ __launch_bounds__(256) void update_march_kernel(UpdArgs<T> a, int ntx, int nty, int ntz,
                                                            int per_xcd)
 {
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void update_march_kernel(UpdArgs<T> a, int ntx
     const int i = bx * MX_TX + threadIdx.x, j = by * MX_TY + threadIdx.y;
     if (i >= G.n[0] || j >= G.n[1]) return;
     const int k0 = bz * MX_KZ, k1 = min(k0 + MX_KZ, G.n[2]);
-    up::march_column(a, i, j, k0, k1);
+    up::march_column<T, BONLY, STAG>(a, i, j, k0, k1);
 }
 
 }  // namespace
@@ -63,8 +63,15 @@ hipError_t launch_update(const T *u0, const T *acc_in, T *acc_out, T *out, const
         int ntx = (G.n[0] + MX_TX - 1) / MX_TX, nty = (G.n[1] + MX_TY - 1) / MX_TY,
             ntz = (G.n[2] + MX_KZ - 1) / MX_KZ;
         int nb = ntx * nty * ntz, per = (nb + NXCD - 1) / NXCD;
-        hipLaunchKernelGGL((update_march_kernel<T>), dim3(per * NXCD), dim3(MX_TX, MX_TY), 0, st, a,
-                           ntx, nty, ntz, per);
+        const dim3 grd(per * NXCD), blk(MX_TX, MX_TY);
+        if (c.bonly && c.stag)
+            hipLaunchKernelGGL((update_march_kernel<T, true, true>), grd, blk, 0, st, a, ntx, nty, ntz, per);
+        else if (c.bonly)
+            hipLaunchKernelGGL((update_march_kernel<T, true, false>), grd, blk, 0, st, a, ntx, nty, ntz, per);
+        else if (c.stag)
+            hipLaunchKernelGGL((update_march_kernel<T, false, true>), grd, blk, 0, st, a, ntx, nty, ntz, per);
+        else
+            hipLaunchKernelGGL((update_march_kernel<T, false, false>), grd, blk, 0, st, a, ntx, nty, ntz, per);
         return hipGetLastError();
     }
     long ncell = (long)G.n[0] * G.n[1] * G.n[2];

@@ -76,17 +76,17 @@ __device__ __forceinline__ T face_bdot(const UpdArgs<T> &a, int n, int fn, int j
     return r;
 }
 
-// RK combination of one cell.
-template <typename T>
-__device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (&L)[8])
+// RK combination of the variables vars[] of one cell: L[v] is the
+// right-hand side of variable v, id the cell's state index; out points at
+// the cell's first output variable (variables osv apart).
+template <typename T, int NV>
+__device__ __forceinline__ void rk_store_vars(const StageCoef &c, long sv, long id, const T *__restrict__ u0,
+                                              const T *acc_in, T *acc_out, T *out, long osv,
+                                              const int (&vars)[NV], const T (&L)[8])
 {
-    const StageCoef &c = a.c;
-    const long sv = a.G.sv;
-    T *const out = a.out + (id + a.odelta);
-    const long osv = a.osv;
     if (c.mode == 0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[v * osv] = L[v];
+        for (int m = 0; m < NV; ++m) out[vars[m] * osv] = L[vars[m]];
         return;
     }
     const T bdt = T(c.bdt), cdt = T(c.cdt);
@@ -94,33 +94,57 @@ __device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (
         const T a0 = T(c.a0), a1 = T(c.a1);
         if (c.a1 != 0.0) {
 #pragma unroll
-            for (int v = 0; v < 8; ++v)
-                out[v * osv] = a0 * a.u0[id + v * sv] + a1 * a.acc_in[id + v * sv] + cdt * L[v];
+            for (int m = 0; m < NV; ++m) {
+                const int v = vars[m];
+                out[v * osv] = a0 * u0[id + v * sv] + a1 * acc_in[id + v * sv] + cdt * L[v];
+            }
         } else {
 #pragma unroll
-            for (int v = 0; v < 8; ++v) out[v * osv] = a0 * a.u0[id + v * sv] + cdt * L[v];
+            for (int m = 0; m < NV; ++m) {
+                const int v = vars[m];
+                out[v * osv] = a0 * u0[id + v * sv] + cdt * L[v];
+            }
         }
         return;
     }
     if (c.s == 0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            T u0 = a.u0[id + v * sv];
-            a.acc_out[id + v * sv] = u0 + bdt * L[v];
-            out[v * osv] = u0 + cdt * L[v];
+        for (int m = 0; m < NV; ++m) {
+            const int v = vars[m];
+            T w = u0[id + v * sv];
+            acc_out[id + v * sv] = w + bdt * L[v];
+            out[v * osv] = w + cdt * L[v];
         }
     } else if (c.s < 3) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            T u0 = a.u0[id + v * sv];
-            T ac = a.acc_in[id + v * sv];
-            a.acc_out[id + v * sv] = ac + bdt * L[v];
-            out[v * osv] = u0 + cdt * L[v];
+        for (int m = 0; m < NV; ++m) {
+            const int v = vars[m];
+            T w = u0[id + v * sv];
+            T ac = acc_in[id + v * sv];
+            acc_out[id + v * sv] = ac + bdt * L[v];
+            out[v * osv] = w + cdt * L[v];
         }
     } else {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[v * osv] = a.acc_in[id + v * sv] + cdt * L[v];
+        for (int m = 0; m < NV; ++m) {
+            const int v = vars[m];
+            out[v * osv] = acc_in[id + v * sv] + cdt * L[v];
+        }
     }
+}
+
+constexpr int ALL_VARS[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
+constexpr int B_VARS[3] = { 4, 5, 6 };
+constexpr int HYDRO_VARS[5] = { 0, 1, 2, 3, 7 };
+
+// RK combination of one cell (all variables, or B only when the hydro part
+// of the stage was done by the fused x sweep).
+template <typename T>
+__device__ __forceinline__ void rk_store(const UpdArgs<T> &a, long id, const T (&L)[8])
+{
+    T *const out = a.out + (id + a.odelta);
+    if (a.c.bonly) rk_store_vars<T, 3>(a.c, a.G.sv, id, a.u0, a.acc_in, a.acc_out, out, a.osv, B_VARS, L);
+    else rk_store_vars<T, 8>(a.c, a.G.sv, id, a.u0, a.acc_in, a.acc_out, out, a.osv, ALL_VARS, L);
 }
 
 // L(U) of one interior cell at pos (any active axes), then the RK store.
@@ -129,11 +153,12 @@ __device__ __forceinline__ void update_cell(const UpdArgs<T> &a, const int (&pos
 {
     const Geom &G = a.G;
     const long id = G.base + pos[0] * G.s[0] + pos[1] * G.s[1] + (long)pos[2] * G.s[2];
-    T L[8];
+    T L[8] = { T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0) };
     // rho, m, E: flux differences (face slots 0..3 and 6 -> variables 0..3, 7)
     const int hs[5] = { 0, 1, 2, 3, 6 }, hv[5] = { 0, 1, 2, 3, 7 };
 #pragma unroll
     for (int h = 0; h < 5; ++h) {
+        if (a.c.bonly) break;
         T acc = T(0);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -152,7 +177,9 @@ __device__ __forceinline__ void update_cell(const UpdArgs<T> &a, const int (&pos
     for (int n = 0; n < 3; ++n) {
         const int a1 = (n + 1) % 3, a2 = (n + 2) % 3;
         T val;
-        if (G.act[n])
+        if (G.act[n] && a.c.stag)
+            val = face_bdot(a, n, pos[n], pos[a1], pos[a2]);     // the lower face itself
+        else if (G.act[n])
             val = T(0.5) * (face_bdot(a, n, pos[n], pos[a1], pos[a2])
                             + face_bdot(a, n, pos[n] + 1, pos[a1], pos[a2]));
         else
@@ -166,7 +193,9 @@ __device__ __forceinline__ void update_cell(const UpdArgs<T> &a, const int (&pos
 // marching in k.  The z-face fluxes and the EMFs of the upper z-level are
 // carried to the next cell; the EMF of every edge is formed exactly as in
 // emf() (same operands, same order), so results equal update_cell's.
-template <typename T>
+// BONLY: only B (CT), the hydro variables having been updated by the fused x
+// sweep; the hydro face components are then neither read nor stored.
+template <typename T, bool BONLY = false, bool STAG = false>
 __device__ __forceinline__ void march_column(const UpdArgs<T> &a, int i, int j, int k0, int k1)
 {
     const Geom &G = a.G;
@@ -208,16 +237,19 @@ __device__ __forceinline__ void march_column(const UpdArgs<T> &a, int i, int j, 
     T Ey0 = ey(k0, i, x5lo0, x5c0), Ey1 = ey(k0, i + 1, x5lo1, x5c1);     // E_y(k, i|i+1, j)
     T Ex0 = ex(j, k0, y4lo0, y4c0), Ex1 = ex(j + 1, k0, y4lo1, y4c1);     // E_x(j|j+1, k, i)
     const int hs[5] = { 0, 1, 2, 3, 6 }, hv[5] = { 0, 1, 2, 3, 7 };
-    T fzlo[5];
+    T fzlo[5] = { T(0), T(0), T(0), T(0), T(0) };
+    if (!BONLY) {
 #pragma unroll
-    for (int h = 0; h < 5; ++h) fzlo[h] = FZ[hs[h] * sz + BZ.idx(i, j, k0)];
+        for (int h = 0; h < 5; ++h) fzlo[h] = FZ[hs[h] * sz + BZ.idx(i, j, k0)];
+    }
 
     for (int k = k0; k < k1; ++k) {
         const long id = G.base + i * G.s[0] + j * G.s[1] + (long)k * G.s[2];
-        T L[8];
+        T L[8] = { T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0) };
         T fzhi[5];
 #pragma unroll
         for (int h = 0; h < 5; ++h) {
+            if (BONLY) break;
             T acc = T(0);
             T fr = FX[hs[h] * sx + BX.idx(i + 1, j, k)], fl = FX[hs[h] * sx + BX.idx(i, j, k)];
             acc -= (fr - fl) * idx;
@@ -243,15 +275,27 @@ __device__ __forceinline__ void march_column(const UpdArgs<T> &a, int i, int j, 
         r = T(0); r -= (Ex3 - Ex1) * idz; r += (Ez11 - Ez01) * idx; byr = r;
         r = T(0); r -= (Ey1 - Ey0) * idx; r += (Ex1 - Ex0) * idy; bzl = r;
         r = T(0); r -= (Ey3 - Ey2) * idx; r += (Ex3 - Ex2) * idy; bzr = r;
-        L[4] = T(0.5) * (bxl + bxr);
-        L[5] = T(0.5) * (byl + byr);
-        L[6] = T(0.5) * (bzl + bzr);
-        rk_store(a, id, L);
+        if (STAG) {
+            // staggered storage: each B slot is its cell's lower face
+            L[4] = bxl;
+            L[5] = byl;
+            L[6] = bzl;
+            (void)bxr; (void)byr; (void)bzr;
+        } else {
+            L[4] = T(0.5) * (bxl + bxr);
+            L[5] = T(0.5) * (byl + byr);
+            L[6] = T(0.5) * (bzl + bzr);
+        }
+        T *const out = a.out + (id + a.odelta);
+        if (BONLY) rk_store_vars<T, 3>(a.c, G.sv, id, a.u0, a.acc_in, a.acc_out, out, a.osv, B_VARS, L);
+        else rk_store_vars<T, 8>(a.c, G.sv, id, a.u0, a.acc_in, a.acc_out, out, a.osv, ALL_VARS, L);
         // carry to level k+1
         Ey0 = Ey2; Ey1 = Ey3; Ex0 = Ex2; Ex1 = Ex3;
         x5c0 = x5h0; x5c1 = x5h1; y4c0 = y4h0; y4c1 = y4h1;
+        if (!BONLY) {
 #pragma unroll
-        for (int h = 0; h < 5; ++h) fzlo[h] = fzhi[h];
+            for (int h = 0; h < 5; ++h) fzlo[h] = fzhi[h];
+        }
     }
 }
 

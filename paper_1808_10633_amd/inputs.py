@@ -91,11 +91,15 @@ def wave_frame():
     return e1, e2, e3
 
 
-def alfven_wave_3d(n, amp=1e-6, gamma=GAMMA, t=0.0):
+def alfven_wave_3d(n, amp=1e-6, gamma=GAMMA, t=0.0, b_faces=False):
     """Alfven wave along (1,1,1) in the periodic unit cube, n^3 cells.
 
     The wave has one wavelength per unit length along each axis
     (k = 2 pi (1,1,1)); it is the exact linear solution shifted by c_A t.
+    b_faces: the B slots hold the field sampled at each cell's lower faces
+    (staggered storage; E uses the mean of the two faces of a cell); the
+    sampled face field has zero face divergence, as k . dB = 0 with equal
+    wavenumbers on every axis.
     Returns (padded conserved state, Alfven speed).
     """
     rho0, p0, bw = alfven_background(gamma)
@@ -115,7 +119,16 @@ def alfven_wave_3d(n, amp=1e-6, gamma=GAMMA, t=0.0):
     v = [-s * c * dBdir[d] for d in range(3)]
     rho = np.full_like(X, rho0)
     p = np.full_like(X, p0)
-    u = conserved(rho, v, B, p, gamma)
+    if not b_faces:
+        u = conserved(rho, v, B, p, gamma)
+        return _pad(u, n, n, n), ca
+    # lower faces of axis d sit half a cell below the centres along d
+    h = 0.5 / n
+    cf = amp * np.cos(phase - 2.0 * math.pi * h)       # the phase moves by -2 pi h along any one axis
+    Bf = [B0[d] + cf * math.sqrt(rho0) * dBdir[d] for d in range(3)]
+    Bc = [0.5 * (Bf[d] + np.roll(Bf[d], -1, axis=2 - d)) for d in range(3)]
+    u = conserved(rho, v, Bc, p, gamma)
+    u[4:7] = np.stack(Bf)
     return _pad(u, n, n, n), ca
 
 
@@ -239,7 +252,7 @@ def _synth(coef, M, dims, shift, torch_mod, device):
 
 def turbulence(dims, mach, beta, seed, *, dx=None, gamma=GAMMA, rho0=1.0, p0=1.0,
                kmin=2.0, kmax=8.0, compressive_fraction=0.0, lognormal_sigma=0.0,
-               device="cpu", dtype=None):
+               device="cpu", dtype=None, b_faces=False):
     """Decaying MHD turbulence box (periodic), returned as a padded conserved
     torch tensor on ``device``.
 
@@ -253,6 +266,9 @@ def turbulence(dims, mach, beta, seed, *, dx=None, gamma=GAMMA, rho0=1.0, p0=1.0
     Density: uniform, or log-normal exp(sigma g - sigma^2/2) for a unit-variance
     random field g.  Pressure p0 uniform.  Seeds: velocity seed, field seed+1,
     density seed+2 (numpy PCG64).
+    b_faces: the B slots hold the face fields themselves (slot d of a cell =
+    the normal field of its lower d-face, zero face divergence), E the energy
+    of the cell-centred field (the mean of the two faces, as without b_faces).
     """
     import torch
     nx, ny, nz = dims
@@ -292,9 +308,18 @@ def turbulence(dims, mach, beta, seed, *, dx=None, gamma=GAMMA, rho0=1.0, p0=1.0
     curl = 1j * np.cross(kt, Ah) * cosf
     dB = _synth(curl, M, dims, (0.5, 0.5, 0.5), torch, device)
     brms = math.sqrt(p0 / beta)
-    dB = dB * (brms / rms(dB))
+    scale = brms / rms(dB)
+    dB = dB * scale
     B0 = math.sqrt(p0 / beta)
     B = [dB[0] + B0, dB[1], dB[2]]
+    if b_faces:
+        # component d at the lower d-faces (shift 0 along d), same modes and scale
+        facec = 1j * np.cross(kt, Ah)
+        Bf = []
+        for d in range(3):
+            sh = tuple(0.0 if e == d and dims[e] > 1 else 0.5 for e in range(3))
+            Bf.append(_synth(facec[:, d:d + 1] * (cosf[:, d:d + 1] if dims[d] == 1 else 1.0), M, dims, sh, torch,
+                             device)[0] * scale + (B0 if d == 0 else 0.0))
 
     if lognormal_sigma > 0.0:
         g = np.random.Generator(np.random.PCG64(seed + 2))
@@ -306,6 +331,8 @@ def turbulence(dims, mach, beta, seed, *, dx=None, gamma=GAMMA, rho0=1.0, p0=1.0
         rho = torch.full((nz, ny, nx), rho0, dtype=torch.float64, device=device)
     p = torch.full_like(rho, p0)
     u = conserved(rho, [v[0], v[1], v[2]], B, p, gamma)
+    if b_faces:
+        u[4:7] = torch.stack(Bf)
     out = torch.zeros(padded_shape(nx, ny, nz), dtype=torch.float64, device=device)
     out[interior_slices(nx, ny, nz)] = u
     return out.to(dtype)

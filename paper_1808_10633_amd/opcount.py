@@ -57,13 +57,30 @@ if __name__ == "__main__":
 DENSE_FLOPS_PER_INTERFACE = 2350
 
 
-def update_bytes_per_cell(esize: int, integrator: str = "rk4") -> float:
+RK4_ARRAYS_PER_STAGE = 13 / 4     # RK4 stage forms: 3, 4, 4, 2 arrays read or written
+
+
+def update_bytes_per_cell(esize: int, integrator: str = "rk4", fused_x: bool = False) -> float:
     """Algorithmic HBM bytes per interior cell of one launch of the flux
     difference / CT / RK update, averaged over the stage forms of a step:
     the 7 stored face components of the three sweeps (one face per cell and
     direction) and the RK arrays: RK4 stages read u0 and write acc, out;
     read u0, acc and write acc, out (twice); read acc and write out
-    (3, 4, 4, 2 arrays: 13/4 on average)."""
-    faces = 7 * 3 * esize
-    arrays = {"rk4": 13 / 4, "ssprk3": (2 + 3 + 3) / 3}[integrator]
-    return faces + arrays * 8 * esize
+    (3, 4, 4, 2 arrays: 13/4 on average).  fused_x: the update of B only
+    (constrained transport; rho, m, E are updated by the fused x sweep):
+    the two transverse-B face components of each direction and the three B
+    variables of the RK arrays."""
+    arrays = {"rk4": RK4_ARRAYS_PER_STAGE, "ssprk3": (2 + 3 + 3) / 3}[integrator]
+    if fused_x:
+        return 2 * 3 * esize + arrays * 3 * esize
+    return 7 * 3 * esize + arrays * 8 * esize
+
+
+def fused_x_bytes_per_cell(esize: int) -> float:
+    """Algorithmic HBM bytes per interior cell of one launch of the x sweep
+    with the rho, m, E update fused in, averaged over the RK4 stage forms:
+    the state read once (8 variables), the two transverse-B components of
+    its x faces written (one face per cell), the y and z faces' rho, m, E
+    fluxes read once (5 components, one face per cell and direction), and
+    the RK arrays of the five hydro variables."""
+    return 8 * esize + 2 * esize + 2 * 5 * esize + RK4_ARRAYS_PER_STAGE * 5 * esize

@@ -24,13 +24,14 @@ WW_ERR_STATE = -7
 _NAMES = {0: "WW_OK", -1: "WW_ERR_INVALID_ARG", -2: "WW_ERR_UNSUPPORTED", -3: "WW_ERR_OOM",
           -4: "WW_ERR_HIP", -5: "WW_ERR_NONPHYSICAL", -6: "WW_ERR_USER_BC", -7: "WW_ERR_STATE"}
 
-ABI_VERSION = 5          # layout of Config below
+ABI_VERSION = 6          # layout of Config below
 WW_FP64 = 0
 WW_FP32_MIXED = 1
 WEIGHTS_JS, WEIGHTS_Z = 0, 1
 RK4, SSPRK3 = 0, 1
 LF_LOCAL, LF_GLOBAL = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_USER = 0, 1, 2
+B_CELL, B_FACE = 0, 1
 
 USER_BC_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p)
 
@@ -43,7 +44,7 @@ class Config(C.Structure):
                 ("user_bc", USER_BC_FN), ("user_bc_ctx", C.c_void_p),
                 ("stream", C.c_void_p), ("device", C.c_int), ("weights", C.c_int),
                 ("integrator", C.c_int), ("lf_speed", C.c_int), ("learned", C.c_int),
-                ("slab_planes", C.c_int)]
+                ("slab_planes", C.c_int), ("b_storage", C.c_int)]
 
 
 class WenoError(RuntimeError):
@@ -134,7 +135,7 @@ def last_error(ctx=None) -> str:
 def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, cfl=0.4,
                 eps=1e-6, precision=WW_FP64, bc=(0, 0, 0, 0, 0, 0), user_bc=None,
                 stream=None, device=0, weights=WEIGHTS_JS, integrator=RK4,
-                lf_speed=LF_LOCAL, learned=0, slab_planes=0) -> Config:
+                lf_speed=LF_LOCAL, learned=0, slab_planes=0, b_storage=B_CELL) -> Config:
     cfg = Config()
     lib().wombat_weno_config_default(C.byref(cfg))
     cfg.nx, cfg.ny, cfg.nz, cfg.ng = nx, ny, nz, 3
@@ -153,6 +154,7 @@ def make_config(nx, ny=1, nz=1, *, dx=None, dy=None, dz=None, gamma=5.0 / 3.0, c
     cfg.lf_speed = lf_speed
     cfg.learned = int(learned)
     cfg.slab_planes = int(slab_planes)
+    cfg.b_storage = int(b_storage)
     return cfg
 
 

@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wombat_weno_abi_version() == 5 == wombat.ABI_VERSION
+    assert lib.wombat_weno_abi_version() == 6 == wombat.ABI_VERSION
 
 
 def _cfg(**kw):
@@ -189,3 +189,19 @@ def test_slab_planes_checks(lib):
         assert lib.wombat_weno_validate_config(C.byref(cfg)) == 0
         assert lib.wombat_weno_init(C.byref(cfg), C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
         assert h.value == 1234
+
+
+def test_b_storage_checks(lib):
+    assert _cfg().b_storage == wombat.B_CELL
+    cfg = _cfg(b_storage=2)
+    assert lib.wombat_weno_validate_config(C.byref(cfg)) == wombat.WW_ERR_INVALID_ARG
+    assert "b_storage" in wombat.last_error()
+    h = C.c_void_p(1234)
+    for kw in (dict(b_storage=1, bc=(1, 1, 0, 0, 0, 0)), dict(b_storage=1, slab_planes=8),
+               dict(b_storage=1, learned=1, precision=wombat.WW_FP32_MIXED)):
+        c2 = _cfg(**kw)
+        assert lib.wombat_weno_validate_config(C.byref(c2)) == 0
+        assert lib.wombat_weno_init(C.byref(c2), C.byref(h)) == wombat.WW_ERR_UNSUPPORTED
+        assert h.value == 1234
+    dims = (C.c_int32 * 3)(16, 16, 16)
+    assert lib.wombat_weno_batch_init(C.byref(_cfg(b_storage=1)), 1, dims, C.byref(h)) == wombat.WW_ERR_UNSUPPORTED

@@ -108,6 +108,55 @@ def test_batch_against_oracle():
         assert err < 1e-11
 
 
+def test_batch_config4_patches_against_oracle():
+    # 16 patches of the 4096-patch workload (edges drawn from {16, 24, 32, 48,
+    # 64} per axis, rms Mach in [0.3, 2], beta in [1, 1e4], seed 4000 + p):
+    # one step of the FP64 batched form against the oracle (<= 1e-11 scaled)
+    # and of the FP32 form against the same oracle step (relative L1 and
+    # Linf per variable, the precision form's error measure)
+    rng = np.random.default_rng(4000)
+    dims = [tuple(int(v) for v in rng.choice([16, 24, 32, 48, 64], size=3)) for _ in range(16)]
+    say(f"[batch] 16 config-4 patches vs the oracle: {dims}")
+    b64 = W.Batch(dims, DX, precision=W.WW_FP64)
+    a64 = b64.new_arena()
+    fill(b64, a64)
+    refs = [b64.view(a64, p).cpu().numpy().copy() for p in range(len(dims))]
+    b32 = W.Batch(dims, DX, precision=W.WW_FP32_MIXED)
+    a32 = b32.new_arena()
+    for p in range(len(dims)):
+        b32.view(a32, p).copy_(b64.view(a64, p).float())
+    b64.step(a64)
+    b32.step(a32)
+    dts, flags = b64.dt()
+    dts32, _ = b32.dt()
+    assert (flags == 0).all()
+    O.set_threads(max(1, min(16, len(os.sched_getaffinity(0)))))
+    worst64 = worst_l1 = worst_linf = 0.0
+    try:
+        for p, (nx, ny, nz) in enumerate(dims):
+            g = O.Grid(nx, ny, nz, DX, DX, DX)
+            dto = O.cfl_dt(g, refs[p])
+            assert abs(dto - dts[p]) <= 1e-14 * dto
+            assert abs(dts32[p] - dto) <= 1e-5 * dto
+            O.rk4_step(g, refs[p], dto)
+            ref = g.interior(refs[p])
+            err, _ = scaled_state_error(g.interior(b64.view(a64, p).cpu().numpy()), ref)
+            worst64 = max(worst64, err)
+            got32 = g.interior(b32.view(a32, p).double().cpu().numpy())
+            for v in range(8):
+                r = np.abs(ref[v])
+                if r.max() == 0:
+                    continue
+                d = np.abs(got32[v] - ref[v])
+                worst_l1 = max(worst_l1, d.mean() / r.mean())
+                worst_linf = max(worst_linf, d.max() / r.max())
+    finally:
+        O.set_threads(1)
+    say(f"  FP64 worst scaled error {worst64:.2e}; FP32 worst relative L1 {worst_l1:.2e}, Linf {worst_linf:.2e}")
+    assert worst64 < 1e-11
+    assert worst_l1 < 1e-5 and worst_linf < 1e-3
+
+
 def test_batch_graph_replays_match_eager():
     say("[batch] graph replays")
     rng = np.random.default_rng(9)

@@ -59,6 +59,21 @@ def test_slab_steps_equal_whole_box_fp32_and_2d_outflow():
     assert torch.equal(ref2[sl2], got2[sl2])
 
 
+def test_fused_x_sweep_equals_separate_update():
+    # rows of >= 86 faces take the x sweep with the rho, m, E update fused in
+    # (the whole-box path); slab mode keeps the separate update: bit for bit
+    n = (100, 24, 30)
+    say("[slab] 100x24x30 FP64 and FP32, 3 steps: fused x sweep vs slabs of 8 (separate update)")
+    for prec, dt_ in ((W.WW_FP64, torch.float64), (W.WW_FP32_MIXED, torch.float32)):
+        u0 = I.turbulence(n, mach=1.5, beta=3.0, seed=85, kmax=6, dx=0.01, device="cuda").to(dt_).contiguous()
+        kw = dict(dx=0.01, dy=0.01, dz=0.01)
+        ref, dref = _steps(n, u0, 3, prec, **kw)
+        got, dgot = _steps(n, u0, 3, prec, slab_planes=8, **kw)
+        sl = I.interior_slices(*n)
+        assert dref == dgot
+        assert torch.equal(ref[sl], got[sl])
+
+
 def test_slab_rhs_and_in_place_stage():
     n = (32, 24, 40)
     say("[slab] 32x24x40 FP64: rhs, and stage 1 written over its input")
