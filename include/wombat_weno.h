@@ -331,7 +331,8 @@ int64_t wombat_weno_batch_patch_offset(const wombat_weno_batch_t *b, int p);
 
 /* One classical RK4 step of every patch of d_arena in place, each with its
  * own CFL time step: four launches of the persistent stage kernel on the
- * configured stream.  Asynchronous; the arena's ghosts are overwritten. */
+ * configured stream.  Asynchronous.  The arena's ghost zones are neither read
+ * nor written: the sweeps take each ghost cell from its periodic image. */
 int wombat_weno_batch_step(wombat_weno_batch_t *b, void *d_arena);
 
 /* As nsteps calls of wombat_weno_batch_step, replaying a HIP graph of one

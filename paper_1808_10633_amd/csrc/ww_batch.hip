@@ -9,10 +9,12 @@
 // work runs out, not when the unluckiest block does.  A block takes
 // each of its patches through the full stage: (stage 0 only) the patch's CFL
 // time step (0, and the patch left unadvanced, if any cell is non-physical),
-// periodic ghost fill, x/y/z characteristic WENO sweeps into the
-// block's own face-flux scratch (y and z first; the flattened x tiles also
-// apply the rho, m, E update), then CT and the B part of the RK update -- the
-// same device functions as the single-box kernels.
+// x/y/z characteristic WENO sweeps into the block's own face-flux scratch
+// (y and z first; the flattened x tiles also apply the rho, m, E update),
+// then CT and the B part of the RK update -- the same device functions as
+// the single-box kernels.  The patches are periodic, and the sweep tiles
+// stage each ghost cell from its periodic image: the ghost zones of the
+// arena are neither filled nor read.
 #include "ww_batch.h"
 #include "ww_sweep_dev.h"
 #include "ww_update_dev.h"
@@ -21,39 +23,6 @@ namespace ww {
 namespace {
 
 constexpr int RB = 256;
-
-template <typename T>
-__device__ __forceinline__ void ghost_fill_patch(T *__restrict__ u, const Geom &G)
-{
-    const int tid = threadIdx.x + sw::TILE * threadIdx.y;
-    for (int ax = 0; ax < 3; ++ax) {
-        const int g = G.g[ax], n = G.n[ax];
-        int lo[3], cnt[3];
-        for (int e = 0; e < 3; ++e) {
-            if (e == ax) { lo[e] = 0; cnt[e] = 2 * g; }
-            else if (e < ax) { lo[e] = -G.g[e]; cnt[e] = G.n[e] + 2 * G.g[e]; }
-            else { lo[e] = 0; cnt[e] = G.n[e]; }
-        }
-        const long total = (long)cnt[0] * cnt[1] * cnt[2];
-        for (long t = tid; t < total; t += RB) {
-            int pos[3];
-            pos[0] = (int)(t % cnt[0]) + lo[0];
-            pos[1] = (int)((t / cnt[0]) % cnt[1]) + lo[1];
-            pos[2] = (int)(t / ((long)cnt[0] * cnt[1])) + lo[2];
-            const int gi = pos[ax];
-            const bool low = gi < g;
-            const int x = low ? gi - g : n + (gi - g);
-            int dst[3] = { pos[0], pos[1], pos[2] }, src[3] = { pos[0], pos[1], pos[2] };
-            dst[ax] = x;
-            src[ax] = low ? x + n : x - n;          // periodic
-            const long di = G.base + dst[0] * G.s[0] + dst[1] * G.s[1] + (long)dst[2] * G.s[2];
-            const long si = G.base + src[0] * G.s[0] + src[1] * G.s[1] + (long)src[2] * G.s[2];
-#pragma unroll
-            for (int v = 0; v < 8; ++v) u[di + v * G.sv] = u[si + v * G.sv];
-        }
-        __syncthreads();
-    }
-}
 
 // CFL time step of one patch (FP64 reduction in fixed order) and its count
 // of non-physical cells.
@@ -112,7 +81,7 @@ __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G,
 }
 
 template <int FT, typename T>
-__global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
+__device__ __forceinline__ void batch_stage(const BatchArgs<T> &a)
 {
     constexpr int C0 = sw::tile_cells<0, FT>(), C1 = sw::tile_cells<1, FT>();
     constexpr int CMAX = (C0 > C1 ? C0 : C1) > sw::XF_MAXC ? (C0 > C1 ? C0 : C1) : sw::XF_MAXC;
@@ -140,7 +109,8 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
         const double dtp = sdt;
         __syncthreads();
         if (dtp == 0.0) continue;        // non-physical patch: left unadvanced
-        ghost_fill_patch<T>(us, G);
+        // no ghost fill: the sweep tiles stage ghost cells from their
+        // periodic images (WRAP)
         T *fx = ff, *fy = ff + NFC * D.F[0].sc, *fz = fy + NFC * D.F[1].sc;
         // the RK stage of this patch, with its own dt
         StageCoef kc;
@@ -155,10 +125,10 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
             long na, nb;
             sw::sweep_tiles<1, FT>(D.F[1], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<1, FT, T>(us, fy, G, D.F[1], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<1, FT, T, false, false, true>(us, fy, G, D.F[1], P, ta, tb, sq);
             sw::sweep_tiles<2, FT>(D.F[2], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T>(us, fz, G, D.F[2], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T, false, false, true>(us, fz, G, D.F[2], P, ta, tb, sq);
         }
         const bool fused = D.xflat != 0;
         if (fused) {
@@ -166,12 +136,12 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
                                kc };
             const long total = (long)D.F[0].cnt[0] * D.F[0].cnt[1] * D.F[0].cnt[2];
             const long nt = (total - 1 + sw::XF_FACES - 2) / (sw::XF_FACES - 1);
-            for (long t = 0; t < nt; ++t) sw::sweep_tile_xflat_fused<T>(us, fx, G, D.F[0], P, t, sq, hx, xf);
+            for (long t = 0; t < nt; ++t) sw::sweep_tile_xflat_fused<T, true>(us, fx, G, D.F[0], P, t, sq, hx, xf);
         } else {
             long na, nb;
             sw::sweep_tiles<0, FT>(D.F[0], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T>(us, fx, G, D.F[0], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T, false, false, true>(us, fx, G, D.F[0], P, ta, tb, sq);
         }
         // flux differences (B only after the fused x sweep), CT, RK
         up::UpdArgs<T> ua;
@@ -186,26 +156,65 @@ __global__ __launch_bounds__(256) void batch_stage_kernel(BatchArgs<T> a)
         ua.osv = G.sv;
         ua.c = kc;
         ua.c.bonly = fused ? 1 : 0;
-        // one thread per cell (marching columns in k cost more registers and
-        // left whole passes of a small patch's columns half idle: measured
-        // 1.5x slower here)
         const int tid = threadIdx.x + sw::TILE * threadIdx.y;
-        const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
-        for (long c = tid; c < ncell; c += RB) {
-            int pos[3];
-            pos[0] = (int)(c % G.n[0]);
-            pos[1] = (int)((c / G.n[0]) % G.n[1]);
-            pos[2] = (int)(c / ((long)G.n[0] * G.n[1]));
-            up::update_cell(ua, pos);
+        if (fused) {
+            // CT and the B stage alone: one thread per (i, j) column segment
+            // of up to KSEG cells, marching in k with the z-level EMFs carried
+            // (every EMF formed once per column instead of once per adjacent
+            // cell, as in update_cell)
+            constexpr int KSEG = 16;
+            const int nseg = (G.n[2] + KSEG - 1) / KSEG;
+            const long ncol = (long)G.n[0] * G.n[1], items = ncol * nseg;
+            for (long t = tid; t < items; t += RB) {
+                const int i = (int)(t % G.n[0]), j = (int)((t / G.n[0]) % G.n[1]);
+                const int k0 = (int)(t / ncol) * KSEG;
+                up::march_column<T, true, false>(ua, i, j, k0, min(k0 + KSEG, G.n[2]));
+            }
+        } else {
+            // every variable: one thread per cell (marching with the hydro
+            // fluxes carried too measured 1.5x slower here: more registers,
+            // and whole passes of a small patch's columns half idle)
+            const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+            for (long c = tid; c < ncell; c += RB) {
+                int pos[3];
+                pos[0] = (int)(c % G.n[0]);
+                pos[1] = (int)((c / G.n[0]) % G.n[1]);
+                pos[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+                up::update_cell(ua, pos);
+            }
         }
         __syncthreads();     // the scratch is reused by the next patch
     }
 }
 
+// FP32: at least two waves per SIMD; left to itself the compiler gives the
+// 16-faces-per-tile kernel an AGPR past 256 registers and one wave per SIMD.
+template <int FT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_stage_f32(BatchArgs<float> a)
+{
+    batch_stage<FT, float>(a);
+}
+
+// FP64: from 8 faces per tile on the LDS tile leaves room for one block per
+// CU anyway, and at 4 two waves per SIMD would spill.
+template <int FT>
+__global__ __launch_bounds__(256) void batch_stage_f64(BatchArgs<double> a)
+{
+    batch_stage<FT, double>(a);
+}
+
+template <int FT, typename T> struct StageKernel;
+template <int FT> struct StageKernel<FT, float> {
+    static constexpr void (*fn)(BatchArgs<float>) = batch_stage_f32<FT>;
+};
+template <int FT> struct StageKernel<FT, double> {
+    static constexpr void (*fn)(BatchArgs<double>) = batch_stage_f64<FT>;
+};
+
 template <int FT, typename T>
 hipError_t launch_ft(const BatchArgs<T> &a, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL((batch_stage_kernel<FT, T>), dim3(nblocks), dim3(sw::TILE, sw::ROWS), 0, st, a);
+    hipLaunchKernelGGL((StageKernel<FT, T>::fn), dim3(nblocks), dim3(sw::TILE, sw::ROWS), 0, st, a);
     return hipGetLastError();
 }
 
@@ -239,10 +248,10 @@ template <typename T>
 hipError_t batch_occupancy(int ft, int *blocks_per_cu)
 {
     switch (ft) {
-    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<16, T>, 256, 0);
-    case 12: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<12, T>, 256, 0);
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<8, T>, 256, 0);
-    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_stage_kernel<4, T>, 256, 0);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, StageKernel<16, T>::fn, 256, 0);
+    case 12: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, StageKernel<12, T>::fn, 256, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, StageKernel<8, T>::fn, 256, 0);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, StageKernel<4, T>::fn, 256, 0);
     }
 }
 

@@ -481,10 +481,15 @@ __device__ __forceinline__ void store_face(T *__restrict__ flux, const FaceBox &
 // tile index ta) x FT consecutive faces (tile index tb); each of the ROWS
 // waves computes faces w, w+ROWS, ...  sq: LDS of NQ * tile_cells<DIR,FT>()
 // elements.  Ends with a block barrier, so consecutive tiles may reuse sq.
+// Periodic image of cell index x (-n <= x < 2n) in 0..n-1.  WRAP tiles (the
+// batched form's periodic patches) stage each ghost cell from its image
+// directly, so the patch needs no ghost fill.
+__device__ __forceinline__ int pwrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
 template <int DIR, int FT>
 __host__ __device__ constexpr int tile_cells() { return DIR == 0 ? ROWS * NCX : TILE * (FT + 5); }
 
-template <int DIR, int FT, typename T, bool WZ = false, bool GLF = false>
+template <int DIR, int FT, typename T, bool WZ = false, bool GLF = false, bool WRAP = false>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restrict__ flux,
                                            const Geom &G, const FaceBox &F, const Phys &P,
                                            int ta, int tb, T *sq)
@@ -506,6 +511,7 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
             int x = f0 - 3 + xi;
             if (row < nrows && x <= nlast) {
                 int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
+                if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
                 long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
                 stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
             }
@@ -533,7 +539,9 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
         for (int rr = w; rr < FT + 5; rr += ROWS) {
             int y = f0 - 3 + rr;
             if (p < npos && y <= nlast) {
-                long id = G.base + ca * G.s[A] + cb * G.s[B] + (long)y * G.s[N];
+                const int wa = WRAP ? pwrap(ca, G.n[A]) : ca, wb = WRAP ? pwrap(cb, G.n[B]) : cb;
+                if (WRAP) y = pwrap(y, G.n[N]);
+                long id = G.base + wa * G.s[A] + wb * G.s[B] + (long)y * G.s[N];
                 stage_cell(u, id, G.sv, cm, P.gamma, sq + rr * TILE + lane, NC);
             }
         }
@@ -638,7 +646,7 @@ __host__ __device__ inline int xflat_cells(int nx, long nrows)
 
 // Stage every cell of the rows that faces g0 .. g0+XF_FACES-1 touch; returns
 // the first row (sq with stride XF_MAXC).
-template <typename T>
+template <typename T, bool WRAP = false>
 __device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F, const Phys &P,
                                             long g0, T *sq)
 {
@@ -654,39 +662,11 @@ __device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom 
         long row = r_lo + c / rowc;
         int x = c % rowc - 3;
         int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
+        if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
         long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
         stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XF_MAXC);
     }
     return r_lo;
-}
-
-template <typename T>
-__device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__restrict__ flux,
-                                                 const Geom &G, const FaceBox &F, const Phys &P,
-                                                 long tile, T *sq)
-{
-    const int nf = F.cnt[0], rowc = G.n[0] + 6;
-    const long nrows = (long)F.cnt[1] * F.cnt[2];
-    const long g0 = tile * XF_FACES;
-    const int tid = threadIdx.x + TILE * threadIdx.y;
-    stage_begin();
-    const long r_lo = xflat_stage(u, G, F, P, g0, sq);
-    __syncthreads();
-    stage_end();
-    const long g = g0 + tid;
-    if (g < nrows * nf) {
-        const long row = g / nf;
-        const int f = (int)(g - row * nf);
-        int pos[3];
-        pos[0] = f;
-        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
-        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
-        T out[7];
-        // stencil cells f-3 .. f+2 sit at row offset f .. f+5
-        face_flux<T>(sq, XF_MAXC, (int)(row - r_lo) * rowc + f, 1, P.gamma, P.igm1, (T)P.eps, out);
-        store_face<0, T>(flux, F, pos, out);
-    }
-    __syncthreads();
 }
 
 // The flattened x sweep with the rho, m, E part of the update fused in (the
@@ -697,7 +677,7 @@ __device__ __forceinline__ void sweep_tile_xflat(const T *__restrict__ u, T *__r
 // differences in the update kernel's order and expressions, then the RK
 // combination.  Only the transverse-B fluxes of the x faces are stored.
 // Ends with a block barrier.
-template <typename T>
+template <typename T, bool WRAP = false>
 __device__ __forceinline__ void sweep_tile_xflat_fused(const T *__restrict__ u, T *__restrict__ flux,
                                                        const Geom &G, const FaceBox &F, const Phys &P,
                                                        long tile, T *sq, T *hx, const XFuse<T> &xf)
@@ -708,7 +688,7 @@ __device__ __forceinline__ void sweep_tile_xflat_fused(const T *__restrict__ u, 
     const long g0 = tile * STRIDE;
     const int tid = threadIdx.x + TILE * threadIdx.y;
     stage_begin();
-    const long r_lo = xflat_stage(u, G, F, P, g0, sq);
+    const long r_lo = xflat_stage<T, WRAP>(u, G, F, P, g0, sq);
     __syncthreads();
     stage_end();
     const long g = g0 + tid;
