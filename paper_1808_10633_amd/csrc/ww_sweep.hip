@@ -12,12 +12,33 @@ namespace {
 // by it.
 #define WW_TWO_WAVES __attribute__((amdgpu_waves_per_eu(2)))
 
+// Hardware block b runs on XCD b % 8 (blocks are dealt round-robin to the
+// eight XCDs, each with its own L2).
+constexpr int NXCD = 8;
+
+// y/z sweeps: tiles (ta: positions of the transverse plane, tb: faces along
+// the sweep axis) are renumbered so that each XCD walks whole columns of
+// tiles, tb fastest.  A tile's 5 halo rows along the sweep axis were staged
+// by the tile before it on the same XCD and come from that XCD's L2.
+__device__ __forceinline__ bool column_tile(long ntile, long nb, long per_xcd, int &ta, int &tb)
+{
+    const long lb = (long)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+    if (lb >= ntile) return false;
+    ta = (int)(lb / nb);
+    tb = (int)(lb - (long)ta * nb);
+    return true;
+}
+
+// DIR 0: 2-D grid (ta, tb); DIR 1, 2: 1-D grid in column order.
 template <int DIR, int FT, typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_kernel(const T *__restrict__ u, T *__restrict__ flux,
-                                                     Geom G, FaceBox F, Phys P)
+                                                     Geom G, FaceBox F, Phys P, long nb, long ntile,
+                                                     long per_xcd)
 {
     __shared__ T sq[sw::NQ * sw::tile_cells<DIR, FT>()];
-    sw::sweep_tile<DIR, FT, T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
+    int ta = blockIdx.x, tb = blockIdx.y;
+    if (DIR != 0 && !column_tile(ntile, nb, per_xcd, ta, tb)) return;
+    sw::sweep_tile<DIR, FT, T, WZ, GLF>(u, flux, G, F, P, ta, tb, sq);
 }
 
 template <typename T, bool WZ, bool GLF>
@@ -28,11 +49,9 @@ __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xseg_kernel(const T *_
     sw::sweep_tile_xseg<T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, sq);
 }
 
-// Hardware block b runs on XCD b % 8 (blocks are dealt round-robin to the
-// eight XCDs, each with its own L2).  The fused x sweep renumbers them so
-// that each XCD walks a contiguous range of tiles: neighbouring rows, whose
-// cells read the same y faces, then meet in one L2.
-constexpr int NXCD = 8;
+// The fused x sweep renumbers blocks so that each XCD walks a contiguous
+// range of tiles: neighbouring rows, whose cells read the same y faces, then
+// meet in one L2.
 
 template <typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xfused_kernel(const T *__restrict__ u,
@@ -65,10 +84,13 @@ constexpr int YZ_PW_F64 = 32;
 
 template <int DIR, int PW, typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_yz_kernel(const T *__restrict__ u, T *__restrict__ flux,
-                                                       Geom G, FaceBox F, Phys P)
+                                                       Geom G, FaceBox F, Phys P, long nb, long ntile,
+                                                       long per_xcd)
 {
     __shared__ T sq[sw::NQ * sw::yz_cells<PW>()];
-    sw::sweep_tile_yz<DIR, PW, T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, blockIdx.y, sq);
+    int ta, tb;
+    if (!column_tile(ntile, nb, per_xcd, ta, tb)) return;
+    sw::sweep_tile_yz<DIR, PW, T, WZ, GLF>(u, flux, G, F, P, ta, tb, sq);
 }
 
 template <int DIR, int FT, typename T, bool WZ, bool GLF>
@@ -79,8 +101,9 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
         constexpr int PW = YZ_PW_F64, B = (DIR == 1) ? 2 : 1;
         const long npos = (long)F.cnt[0] * F.cnt[B];
         const long na = (npos + PW - 1) / PW, nb = (F.cnt[DIR] + 256 / PW - 1) / (256 / PW);
-        hipLaunchKernelGGL((sweep_yz_kernel<DIR == 0 ? 1 : DIR, PW, T, WZ, GLF>), dim3((unsigned)na, (unsigned)nb),
-                           dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P);
+        const long nt = na * nb, per = (nt + NXCD - 1) / NXCD;
+        hipLaunchKernelGGL((sweep_yz_kernel<DIR == 0 ? 1 : DIR, PW, T, WZ, GLF>), dim3((unsigned)(per * NXCD)),
+                           dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P, nb, nt, per);
         return hipGetLastError();
     }
     if (DIR == 0 && F.cnt[0] >= sw::XSEG_MIN) {
@@ -93,8 +116,14 @@ hipError_t launch_dir(const T *u, T *flux, const Geom &G, const FaceBox &F, cons
     }
     long na, nb;
     sw::sweep_tiles<DIR, FT>(F, na, nb);
-    hipLaunchKernelGGL((sweep_kernel<DIR, FT, T, WZ, GLF>), dim3((unsigned)na, (unsigned)nb),
-                       dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P);
+    if (DIR == 0) {
+        hipLaunchKernelGGL((sweep_kernel<DIR, FT, T, WZ, GLF>), dim3((unsigned)na, (unsigned)nb),
+                           dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P, nb, na * nb, 0L);
+    } else {
+        const long nt = na * nb, per = (nt + NXCD - 1) / NXCD;
+        hipLaunchKernelGGL((sweep_kernel<DIR, FT, T, WZ, GLF>), dim3((unsigned)(per * NXCD)),
+                           dim3(sw::TILE, sw::ROWS), 0, st, u, flux, G, F, P, nb, nt, per);
+    }
     return hipGetLastError();
 }
 
