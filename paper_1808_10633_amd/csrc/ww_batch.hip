@@ -161,14 +161,15 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T> &a)
             // CT and the B stage alone: one thread per (i, j) column segment
             // of up to KSEG cells, marching in k with the z-level EMFs carried
             // (every EMF formed once per column instead of once per adjacent
-            // cell, as in update_cell)
+            // cell, as in update_cell), the next level's loads in flight while
+            // a level is computed (two waves per SIMD hide little latency)
             constexpr int KSEG = 16;
             const int nseg = (G.n[2] + KSEG - 1) / KSEG;
             const long ncol = (long)G.n[0] * G.n[1], items = ncol * nseg;
             for (long t = tid; t < items; t += RB) {
                 const int i = (int)(t % G.n[0]), j = (int)((t / G.n[0]) % G.n[1]);
                 const int k0 = (int)(t / ncol) * KSEG;
-                up::march_column<T, true, false>(ua, i, j, k0, min(k0 + KSEG, G.n[2]));
+                up::march_column_b_pipelined<T>(ua, i, j, k0, min(k0 + KSEG, G.n[2]));
             }
         } else {
             // every variable: one thread per cell (marching with the hydro

@@ -299,5 +299,148 @@ __device__ __forceinline__ void march_column(const UpdArgs<T> &a, int i, int j, 
     }
 }
 
+// march_column<T, true, false> (B only, cell-centred B) with the loads of
+// level k+1 issued before the arithmetic of level k, so that a thread keeps
+// one level's loads in flight while it computes: for kernels with few waves
+// per SIMD (the batched stage), where the plain march waits a full memory
+// latency per level.  Same operands, expressions and order as march_column.
+template <typename T>
+struct BLevel {
+    T x5h0, x5h1, y4h0, y4h1;          // FX5(i|i+1, j, k+1), FY4(i, j|j+1, k+1)
+    T z4m, z4c, z4p;                   // FZ4(i-1|i|i+1, j, k+1)
+    T z5m, z5c, z5p;                   // FZ5(i, j-1|j|j+1, k+1)
+    T x4[6];                           // FX4 at (i, j-1), (i, j), (i+1, j-1), (i+1, j), (i, j+1), (i+1, j+1), level k
+    T y5[6];                           // FY5 at (i-1, j), (i, j), (i+1, j), (i-1, j+1), (i, j+1), (i+1, j+1), level k
+    T w0[3], w1[3];                    // u0 and acc_in of B at the cell
+};
+
+template <typename T>
+__device__ __forceinline__ void blevel_load(const UpdArgs<T> &a, int i, int j, int k, bool u0, bool ac,
+                                            BLevel<T> &L)
+{
+    const T *FX = a.ff[0], *FY = a.ff[1], *FZ = a.ff[2];
+    const FaceBox &BX = a.fb[0], &BY = a.fb[1], &BZ = a.fb[2];
+    const long sx = BX.sc, sy = BY.sc, sz = BZ.sc;
+    L.x5h0 = FX[5 * sx + BX.idx(i, j, k + 1)];
+    L.x5h1 = FX[5 * sx + BX.idx(i + 1, j, k + 1)];
+    L.y4h0 = FY[4 * sy + BY.idx(i, j, k + 1)];
+    L.y4h1 = FY[4 * sy + BY.idx(i, j + 1, k + 1)];
+    L.z4m = FZ[4 * sz + BZ.idx(i - 1, j, k + 1)];
+    L.z4c = FZ[4 * sz + BZ.idx(i, j, k + 1)];
+    L.z4p = FZ[4 * sz + BZ.idx(i + 1, j, k + 1)];
+    L.z5m = FZ[5 * sz + BZ.idx(i, j - 1, k + 1)];
+    L.z5c = FZ[5 * sz + BZ.idx(i, j, k + 1)];
+    L.z5p = FZ[5 * sz + BZ.idx(i, j + 1, k + 1)];
+    L.x4[0] = FX[4 * sx + BX.idx(i, j - 1, k)];
+    L.x4[1] = FX[4 * sx + BX.idx(i, j, k)];
+    L.x4[2] = FX[4 * sx + BX.idx(i + 1, j - 1, k)];
+    L.x4[3] = FX[4 * sx + BX.idx(i + 1, j, k)];
+    L.x4[4] = FX[4 * sx + BX.idx(i, j + 1, k)];
+    L.x4[5] = FX[4 * sx + BX.idx(i + 1, j + 1, k)];
+    L.y5[0] = FY[5 * sy + BY.idx(i - 1, j, k)];
+    L.y5[1] = FY[5 * sy + BY.idx(i, j, k)];
+    L.y5[2] = FY[5 * sy + BY.idx(i + 1, j, k)];
+    L.y5[3] = FY[5 * sy + BY.idx(i - 1, j + 1, k)];
+    L.y5[4] = FY[5 * sy + BY.idx(i, j + 1, k)];
+    L.y5[5] = FY[5 * sy + BY.idx(i + 1, j + 1, k)];
+    const Geom &G = a.G;
+    const long id = G.base + i * G.s[0] + j * G.s[1] + (long)k * G.s[2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        L.w0[m] = u0 ? a.u0[id + B_VARS[m] * G.sv] : T(0);
+        L.w1[m] = ac ? a.acc_in[id + B_VARS[m] * G.sv] : T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void march_column_b_pipelined(const UpdArgs<T> &a, int i, int j, int k0, int k1)
+{
+    const Geom &G = a.G;
+    const T *FX = a.ff[0], *FY = a.ff[1], *FZ = a.ff[2];
+    const FaceBox &BX = a.fb[0], &BY = a.fb[1], &BZ = a.fb[2];
+    const long sx = BX.sc, sy = BY.sc, sz = BZ.sc;
+    const T idx = T(G.idl[0]), idy = T(G.idl[1]), idz = T(G.idl[2]);
+    const T q = T(0.25);
+    const StageCoef &c = a.c;
+    const bool u0 = (c.mode == 1 && c.s < 3) || c.mode == 2;
+    const bool ac = (c.mode == 1 && c.s > 0) || (c.mode == 2 && c.a1 != 0.0);
+    const T bdt = T(c.bdt), cdt = T(c.cdt), a0 = T(c.a0), a1 = T(c.a1);
+
+    // carried values at the lower z-level k0 (as march_column)
+    T x5c0 = FX[5 * sx + BX.idx(i, j, k0)], x5c1 = FX[5 * sx + BX.idx(i + 1, j, k0)];
+    T y4c0 = FY[4 * sy + BY.idx(i, j, k0)], y4c1 = FY[4 * sy + BY.idx(i, j + 1, k0)];
+    T Ey0, Ey1, Ex0, Ex1;
+    {
+        const T x5lo0 = FX[5 * sx + BX.idx(i, j, k0 - 1)], x5lo1 = FX[5 * sx + BX.idx(i + 1, j, k0 - 1)];
+        const T y4lo0 = FY[4 * sy + BY.idx(i, j, k0 - 1)], y4lo1 = FY[4 * sy + BY.idx(i, j + 1, k0 - 1)];
+        T t = -FZ[4 * sz + BZ.idx(i - 1, j, k0)];
+        t -= FZ[4 * sz + BZ.idx(i, j, k0)];
+        t += x5lo0;
+        t += x5c0;
+        Ey0 = q * t;
+        t = -FZ[4 * sz + BZ.idx(i, j, k0)];
+        t -= FZ[4 * sz + BZ.idx(i + 1, j, k0)];
+        t += x5lo1;
+        t += x5c1;
+        Ey1 = q * t;
+        t = -y4lo0;
+        t -= y4c0;
+        t += FZ[5 * sz + BZ.idx(i, j - 1, k0)];
+        t += FZ[5 * sz + BZ.idx(i, j, k0)];
+        Ex0 = q * t;
+        t = -y4lo1;
+        t -= y4c1;
+        t += FZ[5 * sz + BZ.idx(i, j, k0)];
+        t += FZ[5 * sz + BZ.idx(i, j + 1, k0)];
+        Ex1 = q * t;
+    }
+    BLevel<T> cur, nxt;
+    blevel_load<T>(a, i, j, k0, u0, ac, cur);
+    for (int k = k0; k < k1; ++k) {
+        if (k + 1 < k1) blevel_load<T>(a, i, j, k + 1, u0, ac, nxt);
+        T t;
+        t = -cur.z4m; t -= cur.z4c; t += x5c0; t += cur.x5h0; const T Ey2 = q * t;
+        t = -cur.z4c; t -= cur.z4p; t += x5c1; t += cur.x5h1; const T Ey3 = q * t;
+        t = -y4c0; t -= cur.y4h0; t += cur.z5m; t += cur.z5c; const T Ex2 = q * t;
+        t = -y4c1; t -= cur.y4h1; t += cur.z5c; t += cur.z5p; const T Ex3 = q * t;
+        t = -cur.x4[0]; t -= cur.x4[1]; t += cur.y5[0]; t += cur.y5[1]; const T Ez00 = q * t;
+        t = -cur.x4[2]; t -= cur.x4[3]; t += cur.y5[1]; t += cur.y5[2]; const T Ez10 = q * t;
+        t = -cur.x4[1]; t -= cur.x4[4]; t += cur.y5[3]; t += cur.y5[4]; const T Ez01 = q * t;
+        t = -cur.x4[3]; t -= cur.x4[5]; t += cur.y5[4]; t += cur.y5[5]; const T Ez11 = q * t;
+        T r, bxl, bxr, byl, byr, bzl, bzr;
+        r = T(0); r -= (Ez01 - Ez00) * idy; r += (Ey2 - Ey0) * idz; bxl = r;
+        r = T(0); r -= (Ez11 - Ez10) * idy; r += (Ey3 - Ey1) * idz; bxr = r;
+        r = T(0); r -= (Ex2 - Ex0) * idz; r += (Ez10 - Ez00) * idx; byl = r;
+        r = T(0); r -= (Ex3 - Ex1) * idz; r += (Ez11 - Ez01) * idx; byr = r;
+        r = T(0); r -= (Ey1 - Ey0) * idx; r += (Ex1 - Ex0) * idy; bzl = r;
+        r = T(0); r -= (Ey3 - Ey2) * idx; r += (Ex3 - Ex2) * idy; bzr = r;
+        const T Lb[3] = { T(0.5) * (bxl + bxr), T(0.5) * (byl + byr), T(0.5) * (bzl + bzr) };
+        const long id = G.base + i * G.s[0] + j * G.s[1] + (long)k * G.s[2];
+        T *const out = a.out + (id + a.odelta);
+        // rk_store_vars's expressions on the preloaded u0 / acc_in values
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const long o = id + B_VARS[m] * G.sv;
+            const long oo = B_VARS[m] * a.osv;
+            if (c.mode == 0) {
+                out[oo] = Lb[m];
+            } else if (c.mode == 2) {
+                out[oo] = c.a1 != 0.0 ? a0 * cur.w0[m] + a1 * cur.w1[m] + cdt * Lb[m] : a0 * cur.w0[m] + cdt * Lb[m];
+            } else if (c.s == 0) {
+                a.acc_out[o] = cur.w0[m] + bdt * Lb[m];
+                out[oo] = cur.w0[m] + cdt * Lb[m];
+            } else if (c.s < 3) {
+                a.acc_out[o] = cur.w1[m] + bdt * Lb[m];
+                out[oo] = cur.w0[m] + cdt * Lb[m];
+            } else {
+                out[oo] = cur.w1[m] + cdt * Lb[m];
+            }
+        }
+        Ey0 = Ey2; Ey1 = Ey3; Ex0 = Ex2; Ex1 = Ex3;
+        x5c0 = cur.x5h0; x5c1 = cur.x5h1; y4c0 = cur.y4h0; y4c1 = cur.y4h1;
+        cur = nxt;
+    }
+}
+
 }  // namespace up
 }  // namespace ww
