@@ -36,32 +36,50 @@ __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G,
     const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
     double mx = 0.0;
     int bad = 0;
-    for (long c = tid; c < ncell; c += RB) {
-        int p[3];
-        p[0] = (int)(c % G.n[0]);
-        p[1] = (int)((c / G.n[0]) % G.n[1]);
-        p[2] = (int)(c / ((long)G.n[0] * G.n[1]));
-        const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
-        double q[8];
-        bool fin = true;
-        for (int v = 0; v < 8; ++v) { q[v] = (double)u[id + v * G.sv]; fin = fin && isfinite(q[v]); }
-        double r = q[0], ir = 1.0 / r;
-        double vx = q[1] * ir, vy = q[2] * ir, vz = q[3] * ir;
-        double b2 = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
-        double pr = (gamma - 1.0) * (q[7] - 0.5 * (q[1] * vx + q[2] * vy + q[3] * vz) - 0.5 * b2);
-        if (!fin || !(r > 0.0) || !(pr > 0.0)) { ++bad; continue; }
-        double a2 = gamma * pr * ir;
-        double v[3] = { vx, vy, vz };
-        double s = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            double bn2 = q[4 + d] * q[4 + d] * ir;
-            double bt2 = b2 * ir - bn2;
-            bt2 = bt2 < 0.0 ? 0.0 : bt2;
-            double dd = a2 - bn2;
-            double cf2 = 0.5 * (a2 + bn2 + bt2 + sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2)));
-            s += (fabs(v[d]) + sqrt(cf2)) * G.idl[d];
+    // DT_IT cells per thread and pass: all their loads first, then the
+    // arithmetic (at two waves per SIMD one cell at a time waits a full
+    // memory latency per cell); the maximum and the count do not depend on
+    // the order
+    constexpr int DT_IT = 4;
+    for (long c0 = tid; c0 < ncell; c0 += DT_IT * RB) {
+        T w[DT_IT][8];
+#pragma unroll
+        for (int it = 0; it < DT_IT; ++it) {
+            const long c = c0 + it * RB;
+            if (c < ncell) {
+                int p[3];
+                p[0] = (int)(c % G.n[0]);
+                p[1] = (int)((c / G.n[0]) % G.n[1]);
+                p[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+                const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) w[it][v] = u[id + v * G.sv];
+            }
         }
-        mx = fmax(mx, s);
+#pragma unroll
+        for (int it = 0; it < DT_IT; ++it) {
+            if (c0 + it * RB >= ncell) continue;
+            double q[8];
+            bool fin = true;
+            for (int v = 0; v < 8; ++v) { q[v] = (double)w[it][v]; fin = fin && isfinite(q[v]); }
+            double r = q[0], ir = 1.0 / r;
+            double vx = q[1] * ir, vy = q[2] * ir, vz = q[3] * ir;
+            double b2 = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+            double pr = (gamma - 1.0) * (q[7] - 0.5 * (q[1] * vx + q[2] * vy + q[3] * vz) - 0.5 * b2);
+            if (!fin || !(r > 0.0) || !(pr > 0.0)) { ++bad; continue; }
+            double a2 = gamma * pr * ir;
+            double v[3] = { vx, vy, vz };
+            double s = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                double bn2 = q[4 + d] * q[4 + d] * ir;
+                double bt2 = b2 * ir - bn2;
+                bt2 = bt2 < 0.0 ? 0.0 : bt2;
+                double dd = a2 - bn2;
+                double cf2 = 0.5 * (a2 + bn2 + bt2 + sqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2)));
+                s += (fabs(v[d]) + sqrt(cf2)) * G.idl[d];
+            }
+            mx = fmax(mx, s);
+        }
     }
     // butterfly over the wave's 64 lanes, then the four waves in order
 #pragma unroll
@@ -125,10 +143,10 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T> &a)
             long na, nb;
             sw::sweep_tiles<1, FT>(D.F[1], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<1, FT, T, false, false, true>(us, fy, G, D.F[1], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<1, FT, T, false, false, true, true>(us, fy, G, D.F[1], P, ta, tb, sq);
             sw::sweep_tiles<2, FT>(D.F[2], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T, false, false, true>(us, fz, G, D.F[2], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<2, FT, T, false, false, true, true>(us, fz, G, D.F[2], P, ta, tb, sq);
         }
         const bool fused = D.xflat != 0;
         if (fused) {
@@ -141,7 +159,7 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T> &a)
             long na, nb;
             sw::sweep_tiles<0, FT>(D.F[0], na, nb);
             for (long tb = 0; tb < nb; ++tb)
-                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T, false, false, true>(us, fx, G, D.F[0], P, ta, tb, sq);
+                for (long ta = 0; ta < na; ++ta) sw::sweep_tile<0, FT, T, false, false, true, true>(us, fx, G, D.F[0], P, ta, tb, sq);
         }
         // flux differences (B only after the fused x sweep), CT, RK
         up::UpdArgs<T> ua;

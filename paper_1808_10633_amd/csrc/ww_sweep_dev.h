@@ -198,14 +198,12 @@ __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5]
               + phi_n<T, LBL, WZ, FOLD>(dm[4], dm[3], dm[2], dm[1], ee, dev);
 }
 
-// Stage one cell: sweep-frame conserved variables and derived quantities.
+// Stage one cell from its sweep-frame conserved variables w (rho, mn, mt1,
+// mt2, Bn, Bt1, Bt2, E): the variables and the derived quantities.
 template <typename T>
-__device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, long sv,
-                                           const int (&cm)[8], double gamma, T *q, int qs)
+__device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q, int qs)
 {
-    T r = u[id + cm[0] * sv], mn = u[id + cm[1] * sv], m1 = u[id + cm[2] * sv],
-      m2 = u[id + cm[3] * sv], bn = u[id + cm[4] * sv], b1 = u[id + cm[5] * sv],
-      b2 = u[id + cm[6] * sv], e = u[id + cm[7] * sv];
+    const T r = w[0], mn = w[1], m1 = w[2], m2 = w[3], bn = w[4], b1 = w[5], b2 = w[6], e = w[7];
     // pressure recovery (kept in FP64 for every storage type)
     double ird = frcp((double)r);
     double pd = (gamma - 1.0) * ((double)e - 0.5 * ((double)mn * mn + (double)m1 * m1 + (double)m2 * m2) * ird
@@ -226,6 +224,45 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
     q[10 * qs] = fsqrt(cf2);
     q[11 * qs] = fsqrt(cs2);
     q[12 * qs] = fsqrt(bn2);
+}
+
+// Stage one cell: its variables read from the state (cm: sweep-frame order).
+template <typename T>
+__device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, long sv,
+                                           const int (&cm)[8], double gamma, T *q, int qs)
+{
+    T w[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) w[v] = u[id + cm[v] * sv];
+    stage_values(w, gamma, q, qs);
+}
+
+// Stage cells c = tid, tid + 256, ... (< ncell, at most IT per thread) of a
+// tile: every global load of the thread's cells first, then the equation of
+// state and LDS stores of each.  A thread's loads are then in flight
+// together rather than one cell's latency after another's, which matters at
+// two waves per SIMD.  cell_id(c, id) gives the state index of tile cell c,
+// false if the cell is not staged; c's LDS slot is sq + c.
+template <int IT, typename T, typename CellId>
+__device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, const int (&cm)[8], double gamma,
+                                           T *sq, int qs, int ncell, CellId cell_id)
+{
+    const int tid = threadIdx.x + 64 * threadIdx.y;
+    T w[IT][8];
+    bool ok[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int c = tid + it * 256;
+        long id = 0;
+        ok[it] = c < ncell && cell_id(c, id);
+        if (ok[it]) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) w[it][v] = u[id + cm[v] * sv];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+        if (ok[it]) stage_values(w[it], gamma, sq + tid + it * 256, qs);
 }
 
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
@@ -475,12 +512,6 @@ __device__ __forceinline__ void store_face(T *__restrict__ flux, const FaceBox &
     flux[6 * F.sc + fi] = out[6];
 }
 
-// One tile of interfaces along axis DIR.  x sweep: ROWS rows (transverse
-// (j,k) pairs, tile index ta) x TILE consecutive faces (tile index tb).
-// y/z sweeps: TILE consecutive positions of the transverse plane (x fastest,
-// tile index ta) x FT consecutive faces (tile index tb); each of the ROWS
-// waves computes faces w, w+ROWS, ...  sq: LDS of NQ * tile_cells<DIR,FT>()
-// elements.  Ends with a block barrier, so consecutive tiles may reuse sq.
 // Periodic image of cell index x (-n <= x < 2n) in 0..n-1.  WRAP tiles (the
 // batched form's periodic patches) stage each ghost cell from its image
 // directly, so the patch needs no ghost fill.
@@ -489,7 +520,15 @@ __device__ __forceinline__ int pwrap(int x, int n) { return x < 0 ? x + n : (x >
 template <int DIR, int FT>
 __host__ __device__ constexpr int tile_cells() { return DIR == 0 ? ROWS * NCX : TILE * (FT + 5); }
 
-template <int DIR, int FT, typename T, bool WZ = false, bool GLF = false, bool WRAP = false>
+// One tile of interfaces along axis DIR.  x sweep: ROWS rows (transverse
+// (j,k) pairs, tile index ta) x TILE consecutive faces (tile index tb).
+// y/z sweeps: TILE consecutive positions of the transverse plane (x fastest,
+// tile index ta) x FT consecutive faces (tile index tb); each of the ROWS
+// waves computes faces w, w+ROWS, ...  sq: LDS of NQ * tile_cells<DIR,FT>()
+// elements.  Ends with a block barrier, so consecutive tiles may reuse sq.
+// LF: stage with stage_tile (a thread's loads first: the batched kernel, at
+// two waves per SIMD, gains 4 %; the single-box FP32 y/z sweeps lose 1 %).
+template <int DIR, int FT, typename T, bool WZ = false, bool GLF = false, bool WRAP = false, bool LF = false>
 __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restrict__ flux,
                                            const Geom &G, const FaceBox &F, const Phys &P,
                                            int ta, int tb, T *sq)
@@ -505,15 +544,22 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
         const int nrows = F.cnt[1] * F.cnt[2];
         const int r0 = ta * ROWS;
         const int f0 = tb * TILE;
-        for (int c = tid; c < ROWS * NCX; c += TILE * ROWS) {
-            int rr = c / NCX, xi = c - rr * NCX;
-            int row = r0 + rr;
+        auto cell_id = [&](int c, long &id) {
+            const int rr = c / NCX, xi = c - rr * NCX;
+            const int row = r0 + rr;
             int x = f0 - 3 + xi;
-            if (row < nrows && x <= nlast) {
-                int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
-                if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
-                long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
-                stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+            if (row >= nrows || x > nlast) return false;
+            int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
+            if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
+            id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
+            return true;
+        };
+        if constexpr (LF) {
+            stage_tile<(ROWS * NCX + 255) / 256>(u, G.sv, cm, P.gamma, sq, NC, ROWS * NCX, cell_id);
+        } else {
+            for (int c = tid; c < ROWS * NCX; c += TILE * ROWS) {
+                long id;
+                if (cell_id(c, id)) stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
             }
         }
         __syncthreads();
@@ -536,13 +582,21 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
         const int p = ta * TILE + lane;
         const int f0 = tb * FT;
         const int ca = F.lo[A] + p % F.cnt[A], cb = F.lo[B] + p / F.cnt[A];
-        for (int rr = w; rr < FT + 5; rr += ROWS) {
-            int y = f0 - 3 + rr;
-            if (p < npos && y <= nlast) {
-                const int wa = WRAP ? pwrap(ca, G.n[A]) : ca, wb = WRAP ? pwrap(cb, G.n[B]) : cb;
-                if (WRAP) y = pwrap(y, G.n[N]);
-                long id = G.base + wa * G.s[A] + wb * G.s[B] + (long)y * G.s[N];
-                stage_cell(u, id, G.sv, cm, P.gamma, sq + rr * TILE + lane, NC);
+        const int wa = WRAP ? pwrap(ca, G.n[A]) : ca, wb = WRAP ? pwrap(cb, G.n[B]) : cb;
+        // cell c = rr * TILE + lane: row rr of the tile at this thread's position
+        auto cell_id = [&](int c, long &id) {
+            int y = f0 - 3 + c / TILE;
+            if (p >= npos || y > nlast) return false;
+            if (WRAP) y = pwrap(y, G.n[N]);
+            id = G.base + wa * G.s[A] + wb * G.s[B] + (long)y * G.s[N];
+            return true;
+        };
+        if constexpr (LF) {
+            stage_tile<(NC + 255) / 256>(u, G.sv, cm, P.gamma, sq, NC, NC, cell_id);
+        } else {
+            for (int c = tid; c < NC; c += TILE * ROWS) {
+                long id;
+                if (cell_id(c, id)) stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
             }
         }
         __syncthreads();
@@ -657,15 +711,14 @@ __device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom 
     long r_hi = (g0 + XF_FACES - 1) / nf;
     if (r_hi > nrows - 1) r_hi = nrows - 1;
     const int ncell = (int)(r_hi - r_lo + 1) * rowc;
-    const int tid = threadIdx.x + TILE * threadIdx.y;
-    for (int c = tid; c < ncell; c += XF_FACES) {
-        long row = r_lo + c / rowc;
+    stage_tile<(XF_MAXC + 255) / 256>(u, G.sv, cm, P.gamma, sq, XF_MAXC, ncell, [&](int c, long &id) {
+        const long row = r_lo + c / rowc;
         int x = c % rowc - 3;
         int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
         if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
-        long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
-        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XF_MAXC);
-    }
+        id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
+        return true;
+    });
     return r_lo;
 }
 
@@ -786,13 +839,12 @@ __device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &
                                            const Phys &P, const XSeg &X, T *sq)
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
-    const int tid = threadIdx.x + TILE * threadIdx.y;
-    for (int c = tid; c < X.o4; c += TILE * ROWS) {
+    stage_tile<(XSEG_CELLS + 255) / 256>(u, G.sv, cm, P.gamma, sq, XSEG_CELLS, X.o4, [&](int c, long &id) {
         const int s = (c >= X.o1) + (c >= X.o2) + (c >= X.o3);
         const int x = X.fa(s) - 3 + (c - X.off(s));
-        const long id = G.base + x * G.s[0] + X.j(s) * G.s[1] + (long)X.k(s) * G.s[2];
-        stage_cell(u, id, G.sv, cm, P.gamma, sq + c, XSEG_CELLS);
-    }
+        id = G.base + x * G.s[0] + X.j(s) * G.s[1] + (long)X.k(s) * G.s[2];
+        return true;
+    });
 }
 
 // Face of thread tid: position and LDS offset of its cell i-2 (stride 1).
@@ -902,6 +954,8 @@ __device__ __forceinline__ void yz_stage(const T *__restrict__ u, const Geom &G,
     const int nlast = G.n[N] + 2;
     const int npos = F.cnt[A] * F.cnt[B];
     const int f0 = tb * FTY;
+    // one cell after another (a thread's loads first, as stage_tile does,
+    // measured 2 % slower here)
     for (int c = tid; c < NC; c += 256) {
         const int rr = c / PW, pc = c - rr * PW;
         const int p = ta * PW + pc, y = f0 - 3 + rr;
