@@ -678,13 +678,20 @@ def config2_form(a, wombat, inputs):
 
 
 def cpu_model():
-    """Host CPU model (lscpu, else /proc/cpuinfo)."""
+    """Host CPU model from lscpu (model name, family and model numbers, CPU and
+    socket counts), else the model name from /proc/cpuinfo."""
     import subprocess
     try:
         txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = {}
         for line in txt.splitlines():
-            if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if "Model name" in f:
+            extra = [f"{k.lower()} {f[k]}" for k in ("CPU family", "Model") if k in f]
+            extra += [f"{f[k]} {k.lower().replace('(s)', 's')}" for k in ("CPU(s)", "Socket(s)") if k in f]
+            return f["Model name"] + (" (" + ", ".join(extra) + ")" if extra else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
