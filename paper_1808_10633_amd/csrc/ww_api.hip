@@ -371,10 +371,11 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
         const long tot = c->nsm_blocks[0] + c->nsm_blocks[1] + c->nsm_blocks[2];
         WW_CHECK(c, hipMemsetAsync(c->nsmooth, 0, sizeof(int32_t) * (tot > 0 ? tot : 1), c->st));
     }
-    // with the fused x sweep the sweeps run y, z, x: the x sweep differences
-    // all three directions' rho, m, E fluxes and applies their RK update, and
-    // the update kernel does constrained transport and B only
-    const bool fuse = c->fuse && !c->router;
+    // with the fused x sweep the sweeps run y, z, x: the x sweep (plain or
+    // routed) differences all three directions' rho, m, E fluxes and applies
+    // their RK update, and the update kernel does constrained transport and
+    // B only
+    const bool fuse = c->fuse;
     const int order[3] = { fuse ? 1 : 0, fuse ? 2 : 1, fuse ? 0 : 2 };
     for (int m = 0; m < 3; ++m) {
         const int d = order[m];
@@ -387,9 +388,12 @@ int operator_t(wombat_weno_t *c, T *us, const T *u0, const T *acc_in, T *acc_out
                     ns += c->nsm_blocks[e];
                     if (c->G.act[e]) mk += c->F[e].sc;
                 }
+                const ww::XFuse<float> xf{ u0, acc_in, acc_out, out, (const float *)c->ff[1], (const float *)c->ff[2],
+                                           c->F[1], c->F[2], k };
                 WW_CHECK(c, ww::launch_routed_sweep(d, (const float *)us, (float *)c->ff[d], c->G, c->F[d], P,
                                                     c->router_pk, c->router_thr, c->router_force, ns,
-                                                    c->queue, c->qcount, mk, c->router_reuse, c->st));
+                                                    c->queue, c->qcount, mk, c->router_reuse,
+                                                    fuse && d == 0 ? &xf : nullptr, c->st));
                 continue;
             }
         }

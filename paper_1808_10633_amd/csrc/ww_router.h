@@ -27,10 +27,13 @@ constexpr int ROUTED_QUEUE_REGIONS = 64;
 // full-WENO pass over the queued troubled interfaces.  queue holds
 // 64 * routed_queue_capacity(dir, F) entries; the 64 counters in qcount are
 // cleared on st first.  mask (F.sc bytes) receives
-// the decisions, or supplies them when reuse is set.
+// the decisions, or supplies them when reuse is set.  xf (x sweep of a 3-D
+// box with rows of at least sweep_x_fused_min_faces() faces, after the y and
+// z sweeps; else nullptr): also the rho, m, E part of the RK stage, as the
+// fused x sweep does; the update then does B only.
 hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
                               const Phys &P, const char *pk, float thr, int force, int32_t *nsmooth,
                               unsigned long long *queue, int32_t *qcount, unsigned char *mask, int reuse,
-                              hipStream_t st);
+                              const XFuse<float> *xf, hipStream_t st);
 
 }  // namespace ww

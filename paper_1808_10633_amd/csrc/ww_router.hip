@@ -578,7 +578,12 @@ __global__ __launch_bounds__(64) void router_sample_kernel(const T *__restrict__
 // take the decisions stored in mask (one byte per face, 1 = troubled) by an
 // earlier evaluation instead of evaluating the network; otherwise store them.
 // Queue entries pack the face position (x+1, y+1, z+1) in 21 bits each.
-template <int DIR>
+// FUSED (x sweep, flattened 256-face tiles, after the y and z sweeps): the
+// tile also applies the rho, m, E update (RK stage xf.c) to every cell whose
+// two x faces lie in the tile and are both smooth, with their fluxes from
+// LDS (the fused x sweep's tail); the other cells are left to
+// xfix_queue_kernel and xfix_bound_kernel.
+template <int DIR, bool FUSED = false>
 __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restrict__ u,
                                                            float *__restrict__ flux, Geom G,
                                                            FaceBox F, Phys P,
@@ -587,8 +592,10 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
                                                            int32_t *__restrict__ nsmooth,
                                                            unsigned long long *__restrict__ queue,
                                                            int32_t *__restrict__ qcount, long qcap,
-                                                           unsigned char *__restrict__ mask, int reuse)
+                                                           unsigned char *__restrict__ mask, int reuse,
+                                                           XFuse<float> xf)
 {
+    static_assert(!FUSED || DIR == 0, "the fused tail belongs to the x sweep");
     // tiles as the plain sweeps: x in flattened 256-face segments (rows of
     // XSEG_MIN faces or more) or 4 rows x 64 faces; y/z 32 positions x 8 faces
     constexpr int NC = DIR == 0 ? sw::XSEG_CELLS : sw::yz_cells<YZ_PW>();
@@ -596,19 +603,23 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
     __shared__ __align__(16) short xs[4 * 32 * XS];     // 32 feature rows per wave
     __shared__ int wcnt[4], wact[4];
     __shared__ long qbase;
+    __shared__ float hx[FUSED ? 5 * 256 : 1];           // FUSED: rho, m, E fluxes of the tile's smooth faces
+    __shared__ unsigned char tfl[FUSED ? 256 : 1];     // FUSED: 1 = no flux of this face in hx
     constexpr int N = DIR;
     const int lane = threadIdx.x, w = threadIdx.y, tid = lane + 64 * w;
     int pos[3], off, cstr;
     bool act;
+    int nface = 0;
     sw::stage_begin();
     if constexpr (DIR == 0) {
         cstr = 1;
-        if (F.cnt[0] >= sw::XSEG_MIN) {
+        if (FUSED || F.cnt[0] >= sw::XSEG_MIN) {
             const sw::XSeg X = sw::xseg_setup(F, blockIdx.x);
             sw::xseg_stage<float>(u, G, F, P, X, sq);
             __syncthreads();
             sw::stage_end();
             act = sw::xseg_face(F, X, tid, pos, off);
+            nface = X.nface;
         } else {
             const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
             const int ta = blockIdx.x, tb = blockIdx.y, nlast = G.n[0] + 2;
@@ -643,13 +654,13 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
     if (force == 0 && reuse) {
         troubled = act && mask[F.idx(pos[0], pos[1], pos[2])] != 0;
     } else if (force == 0) {
-        bf4 xf[12];
+        bf4 xb[12];
         {
             float x[48];
             if (act) router_features<float>(sq, NC, off, cstr, x);
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                xf[k] = act ? pack_bf4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]) : bf4{ 0, 0, 0, 0 };
+                xb[k] = act ? pack_bf4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]) : bf4{ 0, 0, 0, 0 };
         }
         MlpRegs R;
         load_mlp_packed(pk, R);
@@ -661,7 +672,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
             if ((lane >> 5) == h) {
                 bf4 *row = (bf4 *)(g + (lane & 31) * XS);
 #pragma unroll
-                for (int k = 0; k < 12; ++k) row[k] = xf[k];
+                for (int k = 0; k < 12; ++k) row[k] = xb[k];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -676,6 +687,20 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         }
         troubled = !(lg <= thr);                // NaN features count as troubled
         if (act) mask[F.idx(pos[0], pos[1], pos[2])] = troubled ? 1 : 0;
+    }
+    // smooth interfaces: the linear flux (stored below)
+    float lin[7];
+    if (act && !troubled) sw::linear_flux<float>(sq, NC, off, cstr, lin);
+    if constexpr (FUSED) {
+        const bool have = act && !troubled;
+        tfl[tid] = have ? 0 : 1;
+        if (have) {
+            hx[0 * 256 + tid] = lin[0];
+            hx[1 * 256 + tid] = lin[1];
+            hx[2 * 256 + tid] = lin[2];
+            hx[3 * 256 + tid] = lin[3];
+            hx[4 * 256 + tid] = lin[6];
+        }
     }
     // --- troubled interfaces: one queue reservation per block
     const unsigned long long bt = __ballot(act && troubled), ba = __ballot(act);
@@ -698,11 +723,77 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         queue[o] = (unsigned long long)(pos[0] + 1) | ((unsigned long long)(pos[1] + 1) << 21) |
                    ((unsigned long long)(pos[2] + 1) << 42);
     }
-    if (act && !troubled) {
-        float out[7];
-        sw::linear_flux<float>(sq, NC, off, cstr, out);
-        sw::store_face<N, float>(flux, F, pos, out);
+    if (act && !troubled) sw::store_face<N, float>(flux, F, pos, lin);
+    if constexpr (FUSED) {
+        // the cell between faces tid and tid + 1 (same row, interior), both
+        // smooth; hx and tfl were published by the barrier above
+        const int i = pos[0], j = pos[1], k = pos[2];
+        const bool cell = act && tid + 1 < nface && i + 1 < F.cnt[0] && j >= 0 && j < G.n[1] && k >= 0 &&
+                          k < G.n[2] && tfl[tid] == 0 && tfl[tid + 1] == 0;
+        if (cell) {
+            sw::FusedCell<float> fc;
+            sw::fused_cell_load<float>(xf, G, i, j, k, fc);
+            sw::fused_cell_store<float>(xf, G, hx, 256, tid, fc);
+        }
     }
+}
+
+// The rho, m, E update of one cell left by the fused routed x sweep, its x
+// fluxes read back from the flux buffer (every x face stored by then).
+__device__ __forceinline__ void xfix_cell(const float *__restrict__ flux, const Geom &G, const FaceBox &F,
+                                          const XFuse<float> &xf, int i, int j, int k)
+{
+    const int hs[5] = { 0, 1, 2, 3, 6 };
+    float xl[5], xr[5];
+    const long fl = F.idx(i, j, k), fr = F.idx(i + 1, j, k);
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        xl[h] = flux[hs[h] * F.sc + fl];
+        xr[h] = flux[hs[h] * F.sc + fr];
+    }
+    sw::FusedCell<float> fc;
+    sw::fused_cell_load<float>(xf, G, i, j, k, fc);
+    sw::fused_cell_rk<float>(xf, G, xl, xr, fc);
+}
+
+// After the troubled pass: the cells next to the troubled x faces of queue
+// region blockIdx.y.  Each such cell is taken once: the cell right of a
+// troubled face by that face's entry, the cell left of it only if its own
+// lower face is smooth (else that face's entry takes it).
+__global__ __launch_bounds__(128) void xfix_queue_kernel(const float *__restrict__ flux, Geom G, FaceBox F,
+                                                         XFuse<float> xf,
+                                                         const unsigned long long *__restrict__ queue,
+                                                         const int32_t *__restrict__ qcount, long qcap,
+                                                         const unsigned char *__restrict__ mask)
+{
+    const long n = qcount[blockIdx.y];
+    const unsigned long long *qr = queue + blockIdx.y * qcap;
+    for (long e = (long)blockIdx.x * 128 + threadIdx.x; e < n; e += (long)gridDim.x * 128) {
+        const unsigned long long q = qr[e];
+        const int i = (int)(q & 0x1fffff) - 1, j = (int)((q >> 21) & 0x1fffff) - 1, k = (int)(q >> 42) - 1;
+        if (j < 0 || j >= G.n[1] || k < 0 || k >= G.n[2]) continue;
+        if (i < G.n[0]) xfix_cell(flux, G, F, xf, i, j, k);
+        if (i > 0 && mask[F.idx(i - 1, j, k)] == 0) xfix_cell(flux, G, F, xf, i - 1, j, k);
+    }
+}
+
+// The cells whose two x faces are smooth but lie in consecutive tiles (tile
+// t ends with face 256 t + 255), one thread per tile boundary.  Decisions
+// from mask (force -1: every face smooth).
+__global__ __launch_bounds__(256) void xfix_bound_kernel(const float *__restrict__ flux, Geom G, FaceBox F,
+                                                         XFuse<float> xf, const unsigned char *__restrict__ mask,
+                                                         int force, long ntile)
+{
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t + 1 >= ntile) return;
+    const int nf = F.cnt[0];
+    const long g = 256 * t + 255, row = g / nf;
+    const int i = (int)(g - row * nf);
+    if (i + 1 >= nf) return;                                 // the row ends there: no cell
+    const int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
+    if (j < 0 || j >= G.n[1] || k < 0 || k >= G.n[2]) return;
+    if (force == 0 && (mask[F.idx(i, j, k)] != 0 || mask[F.idx(i + 1, j, k)] != 0)) return;
+    xfix_cell(flux, G, F, xf, i, j, k);
 }
 
 // Full characteristic WENO at the queued troubled interfaces: each thread
@@ -827,30 +918,44 @@ long routed_queue_capacity(int dir, const FaceBox &F)
 hipError_t launch_routed_sweep(int dir, const float *u, float *flux, const Geom &G, const FaceBox &F,
                               const Phys &P, const char *pk, float thr, int force, int32_t *nsmooth,
                               unsigned long long *queue, int32_t *qcount, unsigned char *mask, int reuse,
-                              hipStream_t st)
+                              const XFuse<float> *xf, hipStream_t st)
 {
+    const bool fused = xf != nullptr;
+    if (fused && (dir != 0 || F.cnt[0] < sw::XSEG_MIN || !(G.act[0] && G.act[1] && G.act[2])))
+        return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(qcount, 0, sizeof(int32_t) * rt::QREG, st);
     if (e != hipSuccess) return e;
     long na, nb;
     routed_grid(dir, F, na, nb);
     const long cap = routed_queue_capacity(dir, F);
     const dim3 grid((unsigned)na, (unsigned)nb), blk(64, 4), qgrid(32, rt::QREG), qblk(128);
+    const XFuse<float> nofuse{};
     switch (dir) {
     case 0:
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<0>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
-                           nsmooth, queue, qcount, cap, mask, reuse);
+        if (fused)
+            hipLaunchKernelGGL((rt::routed_sweep_kernel<0, true>), grid, blk, 0, st, u, flux, G, F, P, pk, thr,
+                               force, nsmooth, queue, qcount, cap, mask, reuse, *xf);
+        else
+            hipLaunchKernelGGL((rt::routed_sweep_kernel<0, false>), grid, blk, 0, st, u, flux, G, F, P, pk, thr,
+                               force, nsmooth, queue, qcount, cap, mask, reuse, nofuse);
         if (force == 0)
             hipLaunchKernelGGL(rt::troubled_kernel<0>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
+        if (fused && force == 0)
+            hipLaunchKernelGGL(rt::xfix_queue_kernel, qgrid, qblk, 0, st, flux, G, F, *xf, queue, qcount, cap,
+                               mask);
+        if (fused && na > 1)
+            hipLaunchKernelGGL(rt::xfix_bound_kernel, dim3((unsigned)((na - 1 + 255) / 256)), dim3(256), 0, st,
+                               flux, G, F, *xf, mask, force, na);
         break;
     case 1:
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<1>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
-                           nsmooth, queue, qcount, cap, mask, reuse);
+        hipLaunchKernelGGL((rt::routed_sweep_kernel<1, false>), grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
+                           nsmooth, queue, qcount, cap, mask, reuse, nofuse);
         if (force == 0)
             hipLaunchKernelGGL(rt::troubled_kernel<1>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
         break;
     default:
-        hipLaunchKernelGGL(rt::routed_sweep_kernel<2>, grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
-                           nsmooth, queue, qcount, cap, mask, reuse);
+        hipLaunchKernelGGL((rt::routed_sweep_kernel<2, false>), grid, blk, 0, st, u, flux, G, F, P, pk, thr, force,
+                           nsmooth, queue, qcount, cap, mask, reuse, nofuse);
         if (force == 0)
             hipLaunchKernelGGL(rt::troubled_kernel<2>, qgrid, qblk, 0, st, u, flux, G, F, P, queue, qcount, cap);
         break;

@@ -621,9 +621,10 @@ __device__ __forceinline__ void sweep_tile(const T *__restrict__ u, T *__restric
 // fused_cell_load issues the cell's global loads (its y and z faces' fluxes
 // and the RK arrays the stage form reads) before the tile's barrier, so that
 // they are in flight while the other waves finish their face fluxes;
-// fused_cell_store forms L from the two x faces in LDS and the loaded
-// values (the update kernel's expressions and order: x, y, z) and stores
-// the RK combination (rk_store_vars's expressions: identical results).
+// fused_cell_rk forms L from the two x faces' fluxes and the loaded values
+// (the update kernel's expressions and order: x, y, z) and stores the RK
+// combination (rk_store_vars's expressions: identical results);
+// fused_cell_store takes the x fluxes from LDS.
 template <typename T>
 struct FusedCell {
     T fyl[5], fyr[5], fzl[5], fzr[5], w0[5], w1[5];
@@ -653,8 +654,8 @@ __device__ __forceinline__ void fused_cell_load(const XFuse<T> &xf, const Geom &
 }
 
 template <typename T>
-__device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom &G, const T *hx, int nh, int tid,
-                                                 const FusedCell<T> &c)
+__device__ __forceinline__ void fused_cell_rk(const XFuse<T> &xf, const Geom &G, const T (&xl)[5], const T (&xr)[5],
+                                              const FusedCell<T> &c)
 {
     const int hv[5] = { 0, 1, 2, 3, 7 };
     const T idx = T(G.idl[0]), idy = T(G.idl[1]), idz = T(G.idl[2]);
@@ -664,7 +665,7 @@ __device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom 
 #pragma unroll
     for (int h = 0; h < 5; ++h) {
         T L = T(0);
-        L -= (hx[h * nh + tid + 1] - hx[h * nh + tid]) * idx;
+        L -= (xr[h] - xl[h]) * idx;
         L -= (c.fyr[h] - c.fyl[h]) * idy;
         L -= (c.fzr[h] - c.fzl[h]) * idz;
         const long o = id + hv[h] * sv;
@@ -682,6 +683,21 @@ __device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom 
             xf.out[o] = c.w1[h] + cdt * L;
         }
     }
+}
+
+// The cell between tile faces tid and tid + 1, whose rho, m, E fluxes are in
+// LDS (hx, nh apart per component).
+template <typename T>
+__device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom &G, const T *hx, int nh, int tid,
+                                                 const FusedCell<T> &c)
+{
+    T xl[5], xr[5];
+#pragma unroll
+    for (int h = 0; h < 5; ++h) {
+        xl[h] = hx[h * nh + tid];
+        xr[h] = hx[h * nh + tid + 1];
+    }
+    fused_cell_rk<T>(xf, G, xl, xr, c);
 }
 
 // x sweep for short rows (batched patches): the block takes XF_FACES
