@@ -155,3 +155,41 @@ def test_fused_routed_sweep_mixed_routing():
     rel = ((got - want).abs().amax(dim=(1, 2, 3)) / want.abs().amax(dim=(1, 2, 3)).clamp_min(1e-30)).max()
     say(f"  stage accumulator vs dt/3 L: {float(rel):.2e}")
     assert float(rel) < 1e-5
+
+
+def test_fused_routed_steps_match_their_routes():
+    # whole RK4 steps (decisions of the first stage reused in stages 2-4):
+    # every interface troubled equals the plain fused FP32 step up to FMA
+    # contraction, every interface smooth equals the all-linear step bitwise
+    say(f"[learned fused x] {NX}x{NY}x{NZ}: two RK4 steps per route")
+    u = torch.from_numpy(_state(73)).cuda().float().contiguous()
+    plain = W.Context(NX, NY, NZ, dx=H, dy=H, dz=H, precision=W.WW_FP32_MIXED)
+    dt = plain.cfl_dt(u)
+    up = u.clone()
+    for _ in range(2):
+        plain.step(up, dt)
+    theta = R.init_params(13)
+    hi = theta.clone()
+    hi[-1] = 1e4
+    ctx = _ctx(hi, 0)
+    ut = u.clone()
+    for _ in range(2):
+        ctx.step(ut, dt)
+    torch.cuda.synchronize()
+    sl = I.interior_slices(NX, NY, NZ)
+    S = up[sl].abs().amax(dim=(1, 2, 3)).double()
+    e = float(((ut[sl] - up[sl]).abs().amax(dim=(1, 2, 3)).double() / S).max())
+    say(f"  all troubled vs plain: {e:.2e}")
+    assert e < 1e-6 and ctx.router_stats()[2] == 0
+    lo = theta.clone()
+    lo[-1] = -1e4
+    ctx.set_router(lo, 0.5, -1)
+    ul = u.clone()
+    for _ in range(2):
+        ctx.step(ul, dt)
+    ctx.set_router(lo, 0.5, 0)
+    ur = u.clone()
+    for _ in range(2):
+        ctx.step(ur, dt)
+    torch.cuda.synchronize()
+    assert ctx.router_stats()[2] == 0 and torch.equal(ur, ul)
