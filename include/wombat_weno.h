@@ -407,6 +407,10 @@ int wombat_weno_batch_autotune(wombat_weno_batch_t *b, const void *d_arena, cons
  * in the backup array, and if the routed step leaves a non-physical cell it
  * is redone from u^n with full characteristic WENO on every interface
  * (counted in router_stats).  Stages and rhs calls have no fallback.
+ * On 3-D boxes whose x rows have at least 86 faces the sweeps run y, z, x
+ * and the routed x sweep (with two fix-up passes after its troubled pass)
+ * also applies the rho, m, E part of the stage, as the plain route's fused
+ * x sweep does; the result is that of the separate update.
  * WW_ERR_UNSUPPORTED on FP64 contexts (and with WW_WEIGHTS_Z, WW_SSPRK3 or
  * WW_LF_GLOBAL), WW_ERR_INVALID_ARG for a threshold or mode out of range,
  * WW_ERR_STATE without cfg.learned. */
