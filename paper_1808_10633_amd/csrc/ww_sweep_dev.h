@@ -247,12 +247,12 @@ template <int IT, typename T, typename CellId>
 __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, const int (&cm)[8], double gamma,
                                            T *sq, int qs, int ncell, CellId cell_id)
 {
-    const int tid = threadIdx.x + 64 * threadIdx.y;
+    const int tid = threadIdx.x + TILE * threadIdx.y;
     T w[IT][8];
     bool ok[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int c = tid + it * 256;
+        const int c = tid + it * TILE * ROWS;
         long id = 0;
         ok[it] = c < ncell && cell_id(c, id);
         if (ok[it]) {
@@ -262,7 +262,7 @@ __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, con
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-        if (ok[it]) stage_values(w[it], gamma, sq + tid + it * 256, qs);
+        if (ok[it]) stage_values(w[it], gamma, sq + tid + it * TILE * ROWS, qs);
 }
 
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
@@ -851,7 +851,7 @@ __device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile, int stri
 
 // Stage the tile's cells (x sweep frame), sq with stride XSEG_CELLS.
 template <typename T>
-__device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F,
+__device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &G, const FaceBox & /*F*/,
                                            const Phys &P, const XSeg &X, T *sq)
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
@@ -864,7 +864,7 @@ __device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &
 }
 
 // Face of thread tid: position and LDS offset of its cell i-2 (stride 1).
-__device__ __forceinline__ bool xseg_face(const FaceBox &F, const XSeg &X, int tid, int (&pos)[3], int &off)
+__device__ __forceinline__ bool xseg_face(const FaceBox & /*F*/, const XSeg &X, int tid, int (&pos)[3], int &off)
 {
     const int t = tid < X.nface ? tid : X.nface - 1;
     const int s = (t >= X.b1) + (t >= X.b2) + (t >= X.b3);
