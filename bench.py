@@ -33,21 +33,21 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # + ww_update_dev.h (update).
 MEASURED_TRAFFIC = {
     # y sweep (the VALU roofline's kernel) and the fused x sweep
-    ("921dd26e432ca365", "fp64", 512): {"read": 9.423e9, "write": 9.039e9,
-                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("921dd26e432ca365", "fp32", 512): {"read": 4.799e9, "write": 4.703e9,
-                                        "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
-    ("921dd26e432ca365", "fp64_xfused", 512): {"read": 31.11e9, "write": 11.64e9,
-                                               "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("921dd26e432ca365", "fp32_xfused", 512): {"read": 15.30e9, "write": 5.837e9,
-                                               "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
+    ("3fb913d5b1eeb477", "fp64", 512): {"read": 9.424e9, "write": 9.038e9,
+                                      "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
+    ("3fb913d5b1eeb477", "fp32", 512): {"read": 4.799e9, "write": 4.703e9,
+                                      "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
+    ("3fb913d5b1eeb477", "fp64_xfused", 512): {"read": 31.11e9, "write": 11.64e9,
+                                             "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
+    ("3fb913d5b1eeb477", "fp32_xfused", 512): {"read": 15.3e9, "write": 5.837e9,
+                                             "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 MEASURED_UPDATE_TRAFFIC = {
     # B-only update, mean over the profiled launches (RK stage forms and L(U))
-    ("3949a6740f95aeb9", "fp64", 512): {"read": 11.90e9, "write": 5.584e9,
-                                        "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("3949a6740f95aeb9", "fp32", 512): {"read": 5.744e9, "write": 2.817e9,
-                                        "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
+    ("3949a6740f95aeb9", "fp64", 512): {"read": 11.9e9, "write": 5.584e9,
+                                      "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
+    ("3949a6740f95aeb9", "fp32", 512): {"read": 5.743e9, "write": 2.818e9,
+                                      "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 
 # HBM bytes per stage launch of the batched kernel on the 4096-patch set
@@ -55,10 +55,10 @@ MEASURED_UPDATE_TRAFFIC = {
 # valid only for the batched source they were taken on (sha256 of
 # ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
 MEASURED_BATCH_TRAFFIC = {
-    ("9fd38d7d3f5ac3fd", 4096, 4): (85.58e9, 32.20e9),
-    ("9fd38d7d3f5ac3fd", 4096, 8): (79.38e9, 32.73e9),
-    ("9fd38d7d3f5ac3fd", 4096, 12): (80.93e9, 31.49e9),
-    ("9fd38d7d3f5ac3fd", 4096, 16): (78.98e9, 32.48e9),
+    ("e66f5ac9ac739023", 4096, 4): (85.52e9, 32.19e9),
+    ("e66f5ac9ac739023", 4096, 8): (79.29e9, 32.73e9),
+    ("e66f5ac9ac739023", 4096, 12): (80.90e9, 31.49e9),
+    ("e66f5ac9ac739023", 4096, 16): (78.91e9, 32.50e9),
 }
 BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
 
