@@ -438,7 +438,7 @@ __device__ __forceinline__ void march_column_b_pipelined(const UpdArgs<T> &a, in
         }
         Ey0 = Ey2; Ey1 = Ey3; Ex0 = Ex2; Ex1 = Ex3;
         x5c0 = cur.x5h0; x5c1 = cur.x5h1; y4c0 = cur.y4h0; y4c1 = cur.y4h1;
-        cur = nxt;
+        if (k + 1 < k1) cur = nxt;
     }
 }
 
