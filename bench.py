@@ -33,7 +33,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # + ww_update_dev.h (update).
 MEASURED_TRAFFIC = {
     # y sweep (the VALU roofline's kernel) and the fused x sweep
-    ("3fb913d5b1eeb477", "fp64", 512): {"read": 9.424e9, "write": 9.038e9,
+    ("3fb913d5b1eeb477", "fp64", 512): {"read": 9.425e9, "write": 9.038e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
     ("3fb913d5b1eeb477", "fp32", 512): {"read": 4.799e9, "write": 4.703e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
@@ -44,9 +44,9 @@ MEASURED_TRAFFIC = {
 }
 MEASURED_UPDATE_TRAFFIC = {
     # B-only update, mean over the profiled launches (RK stage forms and L(U))
-    ("3949a6740f95aeb9", "fp64", 512): {"read": 11.9e9, "write": 5.584e9,
+    ("cf6b38782c5af04b", "fp64", 512): {"read": 11.9e9, "write": 5.585e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("3949a6740f95aeb9", "fp32", 512): {"read": 5.743e9, "write": 2.818e9,
+    ("cf6b38782c5af04b", "fp32", 512): {"read": 5.743e9, "write": 2.818e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -55,10 +55,10 @@ MEASURED_UPDATE_TRAFFIC = {
 # valid only for the batched source they were taken on (sha256 of
 # ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
 MEASURED_BATCH_TRAFFIC = {
-    ("e66f5ac9ac739023", 4096, 4): (85.52e9, 32.19e9),
-    ("e66f5ac9ac739023", 4096, 8): (79.29e9, 32.73e9),
-    ("e66f5ac9ac739023", 4096, 12): (80.90e9, 31.49e9),
-    ("e66f5ac9ac739023", 4096, 16): (78.91e9, 32.50e9),
+    ("943fbd4c44bd95e6", 4096, 4): (85.52e9, 32.19e9),
+    ("943fbd4c44bd95e6", 4096, 8): (79.29e9, 32.73e9),
+    ("943fbd4c44bd95e6", 4096, 12): (80.90e9, 31.49e9),
+    ("943fbd4c44bd95e6", 4096, 16): (78.93e9, 32.49e9),
 }
 BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
 
