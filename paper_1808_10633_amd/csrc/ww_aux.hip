@@ -36,9 +36,16 @@ __global__ __launch_bounds__(256) void ghost_kernel(T *__restrict__ u, Geom G, i
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     int pos[3];
-    pos[0] = (int)(t % cnt[0]);
-    pos[1] = (int)((t / cnt[0]) % cnt[1]);
-    pos[2] = (int)(t / ((long)cnt[0] * cnt[1]));
+    if (total <= 0x7fffffffL) {                 // 32-bit (uniform branch)
+        const int ti = (int)t;
+        pos[0] = ti % cnt[0];
+        pos[1] = (ti / cnt[0]) % cnt[1];
+        pos[2] = ti / (cnt[0] * cnt[1]);
+    } else {
+        pos[0] = (int)(t % cnt[0]);
+        pos[1] = (int)((t / cnt[0]) % cnt[1]);
+        pos[2] = (int)(t / ((long)cnt[0] * cnt[1]));
+    }
     for (int e = 0; e < 3; ++e) pos[e] += lo[e];
     const int gi = pos[ax];
     const bool low = gi < g;
@@ -115,8 +122,18 @@ __device__ __forceinline__ void block_reduce_k(double (&v)[K])
             for (int i = 1; i < NW; ++i) v[k] = MAX ? fmax(v[k], sv[k][i]) : v[k] + sv[k][i];
 }
 
+// Cell c of the interior in row-major order.  32-bit arithmetic whenever the
+// box has fewer than 2^31 cells (every box that fits in memory: a 64-bit
+// division is a long software sequence on the GPU); the branch is uniform.
 __device__ __forceinline__ void cell_pos(const Geom &G, long c, int (&p)[3])
 {
+    if ((long)G.n[0] * G.n[1] * G.n[2] <= 0x7fffffffL) {
+        const int ci = (int)c;
+        p[0] = ci % G.n[0];
+        p[1] = (ci / G.n[0]) % G.n[1];
+        p[2] = ci / (G.n[0] * G.n[1]);
+        return;
+    }
     p[0] = (int)(c % G.n[0]);
     p[1] = (int)((c / G.n[0]) % G.n[1]);
     p[2] = (int)(c / ((long)G.n[0] * G.n[1]));
@@ -189,9 +206,17 @@ __global__ __launch_bounds__(RB) void lf_partial(const T *__restrict__ u, Geom G
     const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     double m[7] = { 0, 0, 0, 0, 0, 0, 0 };
     for (long c = (long)blockIdx.x * RB + threadIdx.x; c < total; c += (long)gridDim.x * RB) {
-        const int p0 = lo[0] + (int)(c % cnt[0]);
-        const int p1 = lo[1] + (int)((c / cnt[0]) % cnt[1]);
-        const int p2 = lo[2] + (int)(c / ((long)cnt[0] * cnt[1]));
+        int p0, p1, p2;
+        if (total <= 0x7fffffffL) {             // 32-bit (uniform branch)
+            const int ci = (int)c;
+            p0 = lo[0] + ci % cnt[0];
+            p1 = lo[1] + (ci / cnt[0]) % cnt[1];
+            p2 = lo[2] + ci / (cnt[0] * cnt[1]);
+        } else {
+            p0 = lo[0] + (int)(c % cnt[0]);
+            p1 = lo[1] + (int)((c / cnt[0]) % cnt[1]);
+            p2 = lo[2] + (int)(c / ((long)cnt[0] * cnt[1]));
+        }
         const long id = G.base + p0 * G.s[0] + p1 * G.s[1] + (long)p2 * G.s[2];
         double q[8];
         bool fin = true;

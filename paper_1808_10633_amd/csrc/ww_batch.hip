@@ -33,7 +33,7 @@ __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G,
     __shared__ double smx[sw::ROWS];
     __shared__ int sfl[sw::ROWS];
     const int tid = threadIdx.x + sw::TILE * threadIdx.y;
-    const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
+    const int ncell = G.n[0] * G.n[1] * G.n[2];     // < 2^31 for edges of at most 1024
     double mx = 0.0;
     int bad = 0;
     // DT_IT cells per thread and pass: all their loads first, then the
@@ -41,16 +41,16 @@ __device__ __forceinline__ void patch_dt(const T *__restrict__ u, const Geom &G,
     // memory latency per cell); the maximum and the count do not depend on
     // the order
     constexpr int DT_IT = 4;
-    for (long c0 = tid; c0 < ncell; c0 += DT_IT * RB) {
+    for (int c0 = tid; c0 < ncell; c0 += DT_IT * RB) {
         T w[DT_IT][8];
 #pragma unroll
         for (int it = 0; it < DT_IT; ++it) {
-            const long c = c0 + it * RB;
+            const int c = c0 + it * RB;
             if (c < ncell) {
                 int p[3];
-                p[0] = (int)(c % G.n[0]);
-                p[1] = (int)((c / G.n[0]) % G.n[1]);
-                p[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+                p[0] = c % G.n[0];
+                p[1] = (c / G.n[0]) % G.n[1];
+                p[2] = c / (G.n[0] * G.n[1]);
                 const long id = G.base + p[0] * G.s[0] + p[1] * G.s[1] + (long)p[2] * G.s[2];
 #pragma unroll
                 for (int v = 0; v < 8; ++v) w[it][v] = u[id + v * G.sv];
@@ -183,22 +183,22 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T> &a)
             // a level is computed (two waves per SIMD hide little latency)
             constexpr int KSEG = 16;
             const int nseg = (G.n[2] + KSEG - 1) / KSEG;
-            const long ncol = (long)G.n[0] * G.n[1], items = ncol * nseg;
-            for (long t = tid; t < items; t += RB) {
-                const int i = (int)(t % G.n[0]), j = (int)((t / G.n[0]) % G.n[1]);
-                const int k0 = (int)(t / ncol) * KSEG;
+            const int ncol = G.n[0] * G.n[1], items = ncol * nseg;     // 32-bit: edges of at most 1024
+            for (int t = tid; t < items; t += RB) {
+                const int i = t % G.n[0], j = (t / G.n[0]) % G.n[1];
+                const int k0 = t / ncol * KSEG;
                 up::march_column_b_pipelined<T>(ua, i, j, k0, min(k0 + KSEG, G.n[2]));
             }
         } else {
             // every variable: one thread per cell (marching with the hydro
             // fluxes carried too measured 1.5x slower here: more registers,
             // and whole passes of a small patch's columns half idle)
-            const long ncell = (long)G.n[0] * G.n[1] * G.n[2];
-            for (long c = tid; c < ncell; c += RB) {
+            const int ncell = G.n[0] * G.n[1] * G.n[2];
+            for (int c = tid; c < ncell; c += RB) {
                 int pos[3];
-                pos[0] = (int)(c % G.n[0]);
-                pos[1] = (int)((c / G.n[0]) % G.n[1]);
-                pos[2] = (int)(c / ((long)G.n[0] * G.n[1]));
+                pos[0] = c % G.n[0];
+                pos[1] = (c / G.n[0]) % G.n[1];
+                pos[2] = c / (G.n[0] * G.n[1]);
                 up::update_cell(ua, pos);
             }
         }

@@ -702,10 +702,15 @@ __device__ __forceinline__ void fused_cell_store(const XFuse<T> &xf, const Geom 
 
 // x sweep for short rows (batched patches): the block takes XF_FACES
 // consecutive faces of the flattened (row, face) space, stages every cell of
-// the rows they touch (-3..n+2), and each thread computes one face.  The
-// rows touched hold at most xflat_cells(n, rows) cells; sq needs
-// NQ * XF_MAXC elements.
-constexpr int XF_FACES = TILE * ROWS;
+// the rows they touch (-3..n+2), and each thread computes XF_FPT faces (one:
+// two faces per thread spill registers at two waves per SIMD, and the
+// batched FP32 step measured 4% slower).  The rows touched hold at most
+// xflat_cells(n, rows) cells; sq needs NQ * XF_MAXC elements.  Face and row
+// numbers are 32-bit: a patch (edges of at most 1024 cells) has at most
+// 1025 * 1026^2 < 2^31 x faces, and 64-bit divisions are long software
+// sequences on the GPU.
+constexpr int XF_FPT = 1;
+constexpr int XF_FACES = TILE * ROWS * XF_FPT;
 constexpr int XF_MAXC = 544;     // 4-cell rows: at most 53 rows of 10 cells
 __host__ __device__ inline int xflat_cells(int nx, long nrows)
 {
@@ -722,15 +727,15 @@ __device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom 
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
     const int nf = F.cnt[0], rowc = G.n[0] + 6;
-    const long nrows = (long)F.cnt[1] * F.cnt[2];
-    const long r_lo = g0 / nf;
-    long r_hi = (g0 + XF_FACES - 1) / nf;
+    const int nrows = F.cnt[1] * F.cnt[2];
+    const int r_lo = (int)g0 / nf;
+    int r_hi = ((int)g0 + XF_FACES - 1) / nf;
     if (r_hi > nrows - 1) r_hi = nrows - 1;
-    const int ncell = (int)(r_hi - r_lo + 1) * rowc;
+    const int ncell = (r_hi - r_lo + 1) * rowc;
     stage_tile<(XF_MAXC + 255) / 256>(u, G.sv, cm, P.gamma, sq, XF_MAXC, ncell, [&](int c, long &id) {
-        const long row = r_lo + c / rowc;
+        const int row = r_lo + c / rowc;
         int x = c % rowc - 3;
-        int j = F.lo[1] + (int)(row % F.cnt[1]), k = F.lo[2] + (int)(row / F.cnt[1]);
+        int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
         if (WRAP) { x = pwrap(x, G.n[0]); j = pwrap(j, G.n[1]); k = pwrap(k, G.n[2]); }
         id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
         return true;
@@ -741,54 +746,67 @@ __device__ __forceinline__ long xflat_stage(const T *__restrict__ u, const Geom 
 // The flattened x sweep with the rho, m, E part of the update fused in (the
 // batched form's counterpart of sweep_tile_xseg_fused): tiles of XF_FACES
 // faces overlapping by one (tile t starts at face (XF_FACES-1) t), the
-// fluxes' rho, m, E in LDS (hx, 5 x XF_FACES), and thread tid takes the cell
-// between faces tid and tid+1 of one row when the row is interior: x, y, z
-// differences in the update kernel's order and expressions, then the RK
-// combination.  Only the transverse-B fluxes of the x faces are stored.
-// Ends with a block barrier.
+// fluxes' rho, m, E in LDS (hx, 5 x XF_FACES); thread tid takes faces
+// tid + q TILE ROWS (q < XF_FPT) and the cell right of each when the next
+// face is in the same row and the row is interior: x, y, z differences in
+// the update kernel's order and expressions, then the RK combination.  Only
+// the transverse-B fluxes of the x faces are stored.  Ends with a block
+// barrier.
 template <typename T, bool WRAP = false>
 __device__ __forceinline__ void sweep_tile_xflat_fused(const T *__restrict__ u, T *__restrict__ flux,
                                                        const Geom &G, const FaceBox &F, const Phys &P,
                                                        long tile, T *sq, T *hx, const XFuse<T> &xf)
 {
-    constexpr int STRIDE = XF_FACES - 1;
+    constexpr int NT = TILE * ROWS, STRIDE = XF_FACES - 1;
     const int nf = F.cnt[0], rowc = G.n[0] + 6;
-    const long total = (long)F.cnt[1] * F.cnt[2] * nf;
-    const long g0 = tile * STRIDE;
+    const int total = F.cnt[1] * F.cnt[2] * nf;
+    const int g0 = (int)tile * STRIDE;
     const int tid = threadIdx.x + TILE * threadIdx.y;
     stage_begin();
-    const long r_lo = xflat_stage<T, WRAP>(u, G, F, P, g0, sq);
+    const int r_lo = (int)xflat_stage<T, WRAP>(u, G, F, P, g0, sq);
     __syncthreads();
     stage_end();
-    const long g = g0 + tid;
-    const bool valid = g < total;
-    int pos[3] = { 0, 0, 0 };
-    if (valid) {
-        const long row = g / nf;
-        const int f = (int)(g - row * nf);
-        pos[0] = f;
-        pos[1] = F.lo[1] + (int)(row % F.cnt[1]);
-        pos[2] = F.lo[2] + (int)(row / F.cnt[1]);
-        T out[7];
-        face_flux<T>(sq, XF_MAXC, (int)(row - r_lo) * rowc + f, 1, P.gamma, P.igm1, (T)P.eps, out);
-        hx[0 * XF_FACES + tid] = out[0];
-        hx[1 * XF_FACES + tid] = out[1];
-        hx[2 * XF_FACES + tid] = out[2];
-        hx[3 * XF_FACES + tid] = out[3];
-        hx[4 * XF_FACES + tid] = out[6];
-        if (tid < STRIDE || g == total - 1) {
-            const long fi = F.idx(pos[0], pos[1], pos[2]);
-            flux[4 * F.sc + fi] = out[4];
-            flux[5 * F.sc + fi] = out[5];
+    int pos[XF_FPT][3];
+    bool valid[XF_FPT];
+#pragma unroll
+    for (int q = 0; q < XF_FPT; ++q) {
+        const int f = tid + q * NT, g = g0 + f;
+        valid[q] = g < total;
+        pos[q][0] = pos[q][1] = pos[q][2] = 0;
+        if (valid[q]) {
+            const int row = g / nf;
+            pos[q][0] = g - row * nf;
+            pos[q][1] = F.lo[1] + row % F.cnt[1];
+            pos[q][2] = F.lo[2] + row / F.cnt[1];
+            T out[7];
+            face_flux<T>(sq, XF_MAXC, (row - r_lo) * rowc + pos[q][0], 1, P.gamma, P.igm1, (T)P.eps, out);
+            hx[0 * XF_FACES + f] = out[0];
+            hx[1 * XF_FACES + f] = out[1];
+            hx[2 * XF_FACES + f] = out[2];
+            hx[3 * XF_FACES + f] = out[3];
+            hx[4 * XF_FACES + f] = out[6];
+            if (f < STRIDE || g == total - 1) {
+                const long fi = F.idx(pos[q][0], pos[q][1], pos[q][2]);
+                flux[4 * F.sc + fi] = out[4];
+                flux[5 * F.sc + fi] = out[5];
+            }
         }
     }
-    const int i = pos[0], j = pos[1], k = pos[2];
-    const bool cell = valid && tid < STRIDE && g + 1 < total && i + 1 < nf && j >= 0 && j < G.n[1] && k >= 0 &&
-                      k < G.n[2];
-    FusedCell<T> fc;
-    if (cell) fused_cell_load<T>(xf, G, i, j, k, fc);
+    // both cells' global loads in flight before the barrier
+    FusedCell<T> fc[XF_FPT];
+    bool cell[XF_FPT];
+#pragma unroll
+    for (int q = 0; q < XF_FPT; ++q) {
+        const int f = tid + q * NT, g = g0 + f;
+        const int i = pos[q][0], j = pos[q][1], k = pos[q][2];
+        cell[q] = valid[q] && f < STRIDE && g + 1 < total && i + 1 < nf && j >= 0 && j < G.n[1] && k >= 0 &&
+                  k < G.n[2];
+        if (cell[q]) fused_cell_load<T>(xf, G, i, j, k, fc[q]);
+    }
     __syncthreads();
-    if (cell) fused_cell_store<T>(xf, G, hx, XF_FACES, tid, fc);
+#pragma unroll
+    for (int q = 0; q < XF_FPT; ++q)
+        if (cell[q]) fused_cell_store<T>(xf, G, hx, XF_FACES, tid + q * NT, fc[q]);
     __syncthreads();
 }
 
