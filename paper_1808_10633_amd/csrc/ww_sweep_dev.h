@@ -60,6 +60,17 @@ __device__ __forceinline__ float frcp(float x)
     float e = fmaf(-x, r, 1.0f);
     return fmaf(r, e, r);
 }
+// Reciprocal of the nonlinear weights' common denominator: one Newton step in
+// both precisions.  The FP64 estimate is good to about 2^-23, so the step
+// leaves a relative error near 2^-46 in the weights (about 1e-14), far below
+// the scheme's truncation error and the weights' own sensitivity to rounding
+// in the smoothness indicators.
+__device__ __forceinline__ double frcp_w(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float frcp_w(float x) { return frcp(x); }
 
 // Square root in FP64 for finite x >= 0: the hardware reciprocal-square-root
 // estimate, one Goldschmidt step towards g = sqrt(x), h = 1/(2 sqrt(x)), then
@@ -133,7 +144,7 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, const T (&ee)[3], T *dev 
         }
         r0 *= r0; r1 *= r1; r2 *= r2;
         const T A = r1 * r2, B = r0 * r1;
-        const T inv = frcp(fma(T(3), A, fma(T(6), B, r0 * r2)));
+        const T inv = frcp_w(fma(T(3), A, fma(T(6), B, r0 * r2)));
         const T y = fma(T(-2), c, b) + d;
         return fma(fma(A, fma(T(-2), b, a) + c, B * y), inv, T(-1.0 / 12.0) * y);
     }
@@ -363,22 +374,25 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
 
     // rows of L_W, per wave pair: odd (sign-flipping) and even parts, with
     // the 1/2 of the Lax-Friedrichs split folded in (exact power-of-two scale)
-    const T i2a2 = T(0.25 * ia2);
-    const T kf1 = T(af * cfm) * i2a2, kf2 = T(as * csm * sg) * i2a2;
-    const T kf4 = T(as * am_ * isr) * i2a2, kf6 = T(af * irb) * i2a2;
-    const T ks1 = T(as * csm) * i2a2, ks2 = T(af * cfm * sg) * i2a2;
-    const T ks4 = T(af * am_ * isr) * i2a2, ks6 = T(as * irb) * i2a2;
-    const T ka3 = T(0.25 * sg), ka5 = T(0.25 * isr), ke6 = T(ia2), kh = T(0.5);
+    // and the 1/rho and (gamma - 1) of dW/dU: xf below leaves the velocity
+    // components rho times and the pressure 1/(gamma - 1) times too large, and
+    // every row entry that multiplies them carries the inverse factor
+    const double i2a2 = 0.25 * ia2, ir2 = i2a2 * irb, ig2 = i2a2 * gm1 * irb;
+    const T kf1 = T(af * cfm * ir2), kf2 = T(as * csm * sg * ir2);
+    const T kf4 = T(as * am_ * isr * i2a2), kf6 = T(af * ig2);
+    const T ks1 = T(as * csm * ir2), ks2 = T(af * cfm * sg * ir2);
+    const T ks4 = T(af * am_ * isr * i2a2), ks6 = T(as * ig2);
+    const T ka3 = T(0.25 * sg * irb), ka5 = T(0.25 * isr), ke6 = T(ia2 * gm1), kh = T(0.5);
 
-    // dW/dU at the interface state followed by the rotation of the
-    // transverse components onto (beta, perpendicular).
-    const T tv = T(vnb), t1 = T(v1b), t2 = T(v2b), tir = T(irb), tg = T(gm1), th = T(hv2);
+    // dW/dU at the interface state (without the two scales above) followed by
+    // the rotation of the transverse components onto (beta, perpendicular).
+    const T tv = T(vnb), t1 = T(v1b), t2 = T(v2b), th = T(hv2);
     const T tb1 = T(b1b), tb2 = T(b2b), e1 = T(be1), e2 = T(be2);
     auto xf = [&](T (&X)[7]) {
-        T w1 = (X[1] - tv * X[0]) * tir;
-        T w2 = (X[2] - t1 * X[0]) * tir;
-        T w3 = (X[3] - t2 * X[0]) * tir;
-        T w6 = tg * (th * X[0] - tv * X[1] - t1 * X[2] - t2 * X[3] - tb1 * X[4] - tb2 * X[5] + X[6]);
+        T w1 = X[1] - tv * X[0];
+        T w2 = X[2] - t1 * X[0];
+        T w3 = X[3] - t2 * X[0];
+        T w6 = th * X[0] - tv * X[1] - t1 * X[2] - t2 * X[3] - tb1 * X[4] - tb2 * X[5] + X[6];
         T pv = e1 * w2 + e2 * w3, qv = e2 * w2 - e1 * w3;
         T pB = e1 * X[4] + e2 * X[5], qB = e1 * X[5] - e2 * X[4];
         X[1] = w1; X[2] = pv; X[3] = qv; X[4] = pB; X[5] = qB; X[6] = w6;
