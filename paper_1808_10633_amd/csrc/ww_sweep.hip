@@ -16,6 +16,12 @@ namespace {
 // eight XCDs, each with its own L2).
 constexpr int NXCD = 8;
 
+// x sweeps stage the cells' fluxes with the cells (sw::NQ_PRE) in FP32 only:
+// the FP32 fused x sweep ran 1.8 % faster at 512^3.  The FP64 sweeps ran 2 %
+// slower with them (the larger live set spilled at 256 VGPRs), and the FP32
+// y/z tiles lost a block per CU to the larger LDS footprint and ran 5 % slower.
+template <typename T> constexpr bool pre_x() { return sizeof(T) == 4; }
+
 // y/z sweeps: tiles (ta: positions of the transverse plane, tb: faces along
 // the sweep axis) are renumbered so that each XCD walks whole columns of
 // tiles, tb fastest.  A tile's 5 halo rows along the sweep axis were staged
@@ -45,8 +51,8 @@ template <typename T, bool WZ, bool GLF>
 __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xseg_kernel(const T *__restrict__ u, T *__restrict__ flux,
                                                          Geom G, FaceBox F, Phys P)
 {
-    __shared__ T sq[sw::NQ * sw::ROWS * sw::NCX];
-    sw::sweep_tile_xseg<T, WZ, GLF>(u, flux, G, F, P, blockIdx.x, sq);
+    __shared__ T sq[sw::nq<pre_x<T>()>() * sw::XSEG_CELLS];
+    sw::sweep_tile_xseg<T, WZ, GLF, pre_x<T>()>(u, flux, G, F, P, blockIdx.x, sq);
 }
 
 // The fused x sweep renumbers blocks so that each XCD walks a contiguous
@@ -58,11 +64,11 @@ __global__ __launch_bounds__(256) WW_TWO_WAVES void sweep_xfused_kernel(const T 
                                                            T *__restrict__ flux, Geom G, FaceBox F, Phys P,
                                                            XFuse<T> xf, long ntile, long per_xcd)
 {
-    __shared__ T sq[sw::NQ * sw::ROWS * sw::NCX];
+    __shared__ T sq[sw::nq<pre_x<T>()>() * sw::XSEG_CELLS];
     __shared__ T hx[5 * sw::TILE * sw::ROWS];
     const long tile = (long)(blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
     if (tile >= ntile) return;
-    sw::sweep_tile_xseg_fused<T, WZ, GLF>(u, flux, G, F, P, tile, sq, hx, xf);
+    sw::sweep_tile_xseg_fused<T, WZ, GLF, pre_x<T>()>(u, flux, G, F, P, tile, sq, hx, xf);
 }
 
 template <typename T, bool WZ, bool GLF>

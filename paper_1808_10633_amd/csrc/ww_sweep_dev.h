@@ -40,6 +40,12 @@ namespace sw {
 constexpr int NQ = 13;      // staged quantities per cell
 // LDS slots: 0 rho, 1 mn, 2 mt1, 3 mt2, 4 Bn, 5 Bt1, 6 Bt2, 7 E,
 //            8 p, 9 1/rho, 10 c_f, 11 c_s, 12 c_A   (sweep frame)
+// Tiles staged with the cell fluxes (PRE: the FP32 x sweeps) add 13 v_n and
+// 14..19 the sweep-frame flux components 1..6 (the mass flux is m_n): every
+// cell serves six interfaces, and its flux is then formed once per tile
+// instead of once per interface, for 20 quantities of LDS.
+constexpr int NQ_PRE = 20;
+template <bool PRE> constexpr int nq() { return PRE ? NQ_PRE : NQ; }
 constexpr int TILE = 64;    // lanes per row
 constexpr int ROWS = 4;     // waves per block
 constexpr int NCX = TILE + 5;
@@ -209,9 +215,28 @@ __device__ __forceinline__ T weno_field(T cc, const T (&df)[5], const T (&du)[5]
               + phi_n<T, LBL, WZ, FOLD>(dm[4], dm[3], dm[2], dm[1], ee, dev);
 }
 
+// Sweep-frame physical flux of one cell (rho, mn, mt1, mt2, Bt1, Bt2, E
+// components) from its conserved variables w, pressure p and 1/rho; returns
+// the normal velocity.
+template <typename T>
+__device__ __forceinline__ T cell_flux(const T (&w)[8], T p, T ir, T (&F)[7])
+{
+    const T mn = w[1], m1 = w[2], m2 = w[3], bn = w[4], b1 = w[5], b2 = w[6], e = w[7];
+    const T vn = mn * ir, v1 = m1 * ir, v2 = m2 * ir;
+    const T pt = p + T(0.5) * (bn * bn + b1 * b1 + b2 * b2);
+    F[0] = mn;
+    F[1] = mn * vn + pt - bn * bn;
+    F[2] = m1 * vn - bn * b1;
+    F[3] = m2 * vn - bn * b2;
+    F[4] = vn * b1 - v1 * bn;
+    F[5] = vn * b2 - v2 * bn;
+    F[6] = (e + pt) * vn - bn * (vn * bn + v1 * b1 + v2 * b2);
+    return vn;
+}
+
 // Stage one cell from its sweep-frame conserved variables w (rho, mn, mt1,
 // mt2, Bn, Bt1, Bt2, E): the variables and the derived quantities.
-template <typename T>
+template <typename T, bool PRE = false>
 __device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q, int qs)
 {
     const T r = w[0], mn = w[1], m1 = w[2], m2 = w[3], bn = w[4], b1 = w[5], b2 = w[6], e = w[7];
@@ -235,17 +260,24 @@ __device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q
     q[10 * qs] = fsqrt(cf2);
     q[11 * qs] = fsqrt(cs2);
     q[12 * qs] = fsqrt(bn2);
+    if constexpr (PRE) {
+        T F[7];
+        const T vn = cell_flux(w, p, ir, F);
+        q[13 * qs] = vn;
+#pragma unroll
+        for (int c = 1; c < 7; ++c) q[(13 + c) * qs] = F[c];
+    }
 }
 
 // Stage one cell: its variables read from the state (cm: sweep-frame order).
-template <typename T>
+template <typename T, bool PRE = false>
 __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, long sv,
                                            const int (&cm)[8], double gamma, T *q, int qs)
 {
     T w[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) w[v] = u[id + cm[v] * sv];
-    stage_values(w, gamma, q, qs);
+    stage_values<T, PRE>(w, gamma, q, qs);
 }
 
 // Stage cells c = tid, tid + 256, ... (< ncell, at most IT per thread) of a
@@ -254,7 +286,7 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // together rather than one cell's latency after another's, which matters at
 // two waves per SIMD.  cell_id(c, id) gives the state index of tile cell c,
 // false if the cell is not staged; c's LDS slot is sq + c.
-template <int IT, typename T, typename CellId>
+template <int IT, bool PRE = false, typename T, typename CellId>
 __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, const int (&cm)[8], double gamma,
                                            T *sq, int qs, int ncell, CellId cell_id)
 {
@@ -273,7 +305,7 @@ __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, con
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-        if (ok[it]) stage_values(w[it], gamma, sq + tid + it * TILE * ROWS, qs);
+        if (ok[it]) stage_values<T, PRE>(w[it], gamma, sq + tid + it * TILE * ROWS, qs);
 }
 
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
@@ -284,7 +316,8 @@ __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, con
 // GLF: the LF speed of field s is ag[s] (global speeds of the sweep, an
 // ablation) instead of the largest |lambda^s| over the six cells.
 // FOLD: phi_n's folded form (off where the register budget is exhausted).
-template <typename T, bool LBL = false, bool WZ = false, bool GLF = false, bool FOLD = true>
+// PRE: the cells were staged with their fluxes and v_n (NQ_PRE quantities).
+template <typename T, bool LBL = false, bool WZ = false, bool GLF = false, bool FOLD = true, bool PRE = false>
 __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int off, int cstr,
                                           double gamma, double igm1, T eps, T (&out)[7],
                                           T *dev = nullptr, const double *ag = nullptr)
@@ -294,15 +327,31 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     T Fp[7], Up[7];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        T r = QQ(0, j), mn = QQ(1, j), m1 = QQ(2, j), m2 = QQ(3, j);
-        T bn = QQ(4, j), b1 = QQ(5, j), b2 = QQ(6, j), e = QQ(7, j);
-        T p = QQ(8, j), ir = QQ(9, j), cf = QQ(10, j), cs = QQ(11, j), ca = QQ(12, j);
-        T vn = mn * ir, v1 = m1 * ir, v2 = m2 * ir;
-        T pt = p + T(0.5) * (bn * bn + b1 * b1 + b2 * b2);
-        T Fj[7] = { mn, mn * vn + pt - bn * bn, m1 * vn - bn * b1, m2 * vn - bn * b2,
-                    vn * b1 - v1 * bn, vn * b2 - v2 * bn,
-                    (e + pt) * vn - bn * (vn * bn + v1 * b1 + v2 * b2) };
-        T Uj[7] = { r, mn, m1, m2, b1, b2, e };
+        T vn, cf, cs, ca, Fj[7], Uj[7];
+        if constexpr (PRE) {
+            const T r = QQ(0, j), mn = QQ(1, j), m1 = QQ(2, j), m2 = QQ(3, j);
+            const T b1 = QQ(5, j), b2 = QQ(6, j), e = QQ(7, j);
+            vn = QQ(13, j); cf = QQ(10, j); cs = QQ(11, j); ca = QQ(12, j);
+            Fj[0] = mn;
+#pragma unroll
+            for (int c = 1; c < 7; ++c) Fj[c] = QQ(13 + c, j);
+            Uj[0] = r; Uj[1] = mn; Uj[2] = m1; Uj[3] = m2; Uj[4] = b1; Uj[5] = b2; Uj[6] = e;
+        } else {
+            // cell_flux's expressions, written out and in this order (the FP64
+            // kernels' register allocation at 256 VGPRs follows the order of
+            // the LDS reads)
+            T r = QQ(0, j), mn = QQ(1, j), m1 = QQ(2, j), m2 = QQ(3, j);
+            T bn = QQ(4, j), b1 = QQ(5, j), b2 = QQ(6, j), e = QQ(7, j);
+            T p = QQ(8, j), ir = QQ(9, j);
+            cf = QQ(10, j); cs = QQ(11, j); ca = QQ(12, j);
+            vn = mn * ir;
+            T v1 = m1 * ir, v2 = m2 * ir;
+            T pt = p + T(0.5) * (bn * bn + b1 * b1 + b2 * b2);
+            Fj[0] = mn; Fj[1] = mn * vn + pt - bn * bn; Fj[2] = m1 * vn - bn * b1; Fj[3] = m2 * vn - bn * b2;
+            Fj[4] = vn * b1 - v1 * bn; Fj[5] = vn * b2 - v2 * bn;
+            Fj[6] = (e + pt) * vn - bn * (vn * bn + v1 * b1 + v2 * b2);
+            Uj[0] = r; Uj[1] = mn; Uj[2] = m1; Uj[3] = m2; Uj[4] = b1; Uj[5] = b2; Uj[6] = e;
+        }
         T lam[7] = { fabs(vn - cf), fabs(vn - ca), fabs(vn - cs), fabs(vn),
                      fabs(vn + cs), fabs(vn + ca), fabs(vn + cf) };
 #pragma unroll
@@ -333,15 +382,23 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
     double b2b = 0.5 * ((double)QQ(6, 2) + (double)QQ(6, 3));
     double pb = 0.5 * ((double)QQ(8, 2) + (double)QQ(8, 3));
 #undef QQ
-    double irb = frcp(rb);
+    // FP32 storage: 1/rho, a and 1/a^2, c_f and 1/c_f^2 from one reciprocal
+    // square root each, and c_s = a c_A / c_f with c_A = |B_n| rho^-1/2.  The
+    // FP64 kernels sit at the 256-VGPR limit, where the longer live ranges of
+    // that form spill; they take each quantity separately.
+    constexpr bool LEAN = sizeof(T) == 4;
+    double irb, isr = 0.0;
+    if constexpr (LEAN) { isr = frsq(rb); irb = isr * isr; }
+    else irb = frcp(rb);
     double a2 = gamma * pb * irb;
     double bn2 = bnb * bnb * irb;
     double bt2 = (b1b * b1b + b2b * b2b) * irb;
     double dd = a2 - bn2;
     double sqD = fsqrt(dd * dd + bt2 * (2.0 * a2 + 2.0 * bn2 + bt2));
     double cf2 = 0.5 * (a2 + bn2 + bt2 + sqD);
-    double icf2 = frcp(cf2);
-    double cs2 = a2 * bn2 * icf2;
+    double icf2, rcf = 0.0, cs2 = 0.0;
+    if constexpr (LEAN) { rcf = frsq(cf2); icf2 = rcf * rcf; }
+    else { icf2 = frcp(cf2); cs2 = a2 * bn2 * icf2; }
     double af, as;
     if (sqD <= 1e-12 * (a2 + bn2 + bt2)) {
         af = 1.0; as = 0.0;
@@ -367,8 +424,16 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
         be1 = 1.0; be2 = 0.0;
     }
     double sg = (bnb >= 0.0) ? 1.0 : -1.0;
-    double cfm = fsqrt(cf2), csm = fsqrt(cs2), am_ = fsqrt(a2);
-    double isr = frsq(rb), sr = rb * isr, ia2 = frcp(a2);
+    double cfm, csm, am_, ia2;
+    if constexpr (LEAN) {
+        const double ra = frsq(a2);
+        am_ = a2 * ra; ia2 = ra * ra;
+        cfm = cf2 * rcf; csm = am_ * fabs(bnb) * isr * rcf;
+    } else {
+        cfm = fsqrt(cf2); csm = fsqrt(cs2); am_ = fsqrt(a2);
+        isr = frsq(rb); ia2 = frcp(a2);
+    }
+    const double sr = rb * isr;
     double gm1 = gamma - 1.0;
     double hv2 = 0.5 * (vnb * vnb + v1b * v1b + v2b * v2b);
 
@@ -882,12 +947,12 @@ __device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile, int stri
 }
 
 // Stage the tile's cells (x sweep frame), sq with stride XSEG_CELLS.
-template <typename T>
+template <typename T, bool PRE = false>
 __device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &G, const FaceBox & /*F*/,
                                            const Phys &P, const XSeg &X, T *sq)
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
-    stage_tile<(XSEG_CELLS + 255) / 256>(u, G.sv, cm, P.gamma, sq, XSEG_CELLS, X.o4, [&](int c, long &id) {
+    stage_tile<(XSEG_CELLS + 255) / 256, PRE>(u, G.sv, cm, P.gamma, sq, XSEG_CELLS, X.o4, [&](int c, long &id) {
         const int s = (c >= X.o1) + (c >= X.o2) + (c >= X.o3);
         const int x = X.fa(s) - 3 + (c - X.off(s));
         id = G.base + x * G.s[0] + X.j(s) * G.s[1] + (long)X.k(s) * G.s[2];
@@ -908,14 +973,14 @@ __device__ __forceinline__ bool xseg_face(const FaceBox & /*F*/, const XSeg &X, 
     return tid < X.nface;
 }
 
-template <typename T, bool WZ = false, bool GLF = false>
+template <typename T, bool WZ = false, bool GLF = false, bool PRE = false>
 __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__restrict__ flux,
                                                 const Geom &G, const FaceBox &F, const Phys &P,
                                                 long tile, T *sq)
 {
     stage_begin();
     const XSeg X = xseg_setup(F, tile);
-    xseg_stage<T>(u, G, F, P, X, sq);
+    xseg_stage<T, PRE>(u, G, F, P, X, sq);
     __syncthreads();
     stage_end();
     int pos[3], off;
@@ -925,8 +990,8 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
         // live across the fields, which pushes this kernel past 256 VGPRs
         // (a scratch spill of ~2.7 GB of writes per 512^3 launch); the
         // plain form fits and runs as fast
-        face_flux<T, false, WZ, GLF, (sizeof(T) == 4)>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out,
-                                                         nullptr, P.ag);
+        face_flux<T, false, WZ, GLF, (sizeof(T) == 4), PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps,
+                                                              out, nullptr, P.ag);
         store_face<0, T>(flux, F, pos, out);
     }
 }
@@ -943,14 +1008,14 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
 // stored, once per face (the overlapping face by the next tile).
 constexpr int XFUSE_STRIDE = TILE * ROWS - 1;
 
-template <typename T, bool WZ = false, bool GLF = false>
+template <typename T, bool WZ = false, bool GLF = false, bool PRE = false>
 __device__ __forceinline__ void sweep_tile_xseg_fused(const T *__restrict__ u, T *__restrict__ flux,
                                                       const Geom &G, const FaceBox &F, const Phys &P,
                                                       long tile, T *sq, T *hx, const XFuse<T> &xf)
 {
     stage_begin();
     const XSeg X = xseg_setup(F, tile, XFUSE_STRIDE);
-    xseg_stage<T>(u, G, F, P, X, sq);
+    xseg_stage<T, PRE>(u, G, F, P, X, sq);
     __syncthreads();
     stage_end();
     const int tid = threadIdx.x + TILE * threadIdx.y;
@@ -959,8 +1024,8 @@ __device__ __forceinline__ void sweep_tile_xseg_fused(const T *__restrict__ u, T
     const bool valid = xseg_face(F, X, tid, pos, off);
     if (valid) {
         T out[7];
-        face_flux<T, false, WZ, GLF, (sizeof(T) == 4)>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out,
-                                                         nullptr, P.ag);
+        face_flux<T, false, WZ, GLF, (sizeof(T) == 4), PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps,
+                                                              out, nullptr, P.ag);
         hx[0 * NH + tid] = out[0];
         hx[1 * NH + tid] = out[1];
         hx[2 * NH + tid] = out[2];
