@@ -66,17 +66,17 @@ __device__ __forceinline__ float frcp(float x)
     float e = fmaf(-x, r, 1.0f);
     return fmaf(r, e, r);
 }
-// Reciprocal of the nonlinear weights' common denominator: one Newton step in
-// both precisions.  The FP64 estimate is good to about 2^-23, so the step
-// leaves a relative error near 2^-46 in the weights (about 1e-14), far below
-// the scheme's truncation error and the weights' own sensitivity to rounding
-// in the smoothness indicators.
+// Reciprocal of the nonlinear weights' common denominator.  FP64: one Newton
+// step on the estimate, which is good to about 2^-23, leaving a relative error
+// near 2^-46 in the weights (about 1e-14), far below the scheme's truncation
+// error and the weights' own sensitivity to rounding in the smoothness
+// indicators.  FP32: the estimate itself (within 1 ulp).
 __device__ __forceinline__ double frcp_w(double x)
 {
     const double r = __builtin_amdgcn_rcp(x);
     return fma(r, fma(-x, r, 1.0), r);
 }
-__device__ __forceinline__ float frcp_w(float x) { return frcp(x); }
+__device__ __forceinline__ float frcp_w(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Square root in FP64 for finite x >= 0: the hardware reciprocal-square-root
 // estimate, one Goldschmidt step towards g = sqrt(x), h = 1/(2 sqrt(x)), then
@@ -145,7 +145,7 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, const T (&ee)[3], T *dev 
         T r2 = fma(d, fma(T(4 * SQ12), d, T(-11 * SQ12) * c), fma(T(10 * SQ12), c2, ee[2]));
         if constexpr (sizeof(T) == 4) {
             // FP32: keep the products of the squares in range (see below)
-            const T s = frcp(fmax(r0, fmax(r1, r2)));
+            const T s = __builtin_amdgcn_rcpf(fmax(r0, fmax(r1, r2)));
             r0 *= s; r1 *= s; r2 *= s;
         }
         r0 *= r0; r1 *= r1; r2 *= r2;
@@ -166,9 +166,10 @@ __device__ __forceinline__ T phi_n(T a, T b, T c, T d, const T (&ee)[3], T *dev 
     T q2 = fma(d, fma(T(4), d, T(-11) * c), fma(T(10), c2, e4));
     if constexpr (sizeof(T) == 4) {
         // FP32: the products of four (epsilon + IS)/4 below overflow once IS
-        // passes ~5e9 (strong blasts); scaled by their largest they stay in
-        // (0, 1], and the weights, which depend only on ratios, are unchanged
-        const T s = frcp(fmax(q0, fmax(q1, q2)));
+        // passes ~5e9 (strong blasts); scaled by (about) their largest they
+        // stay in (0, 1], and the weights, which depend only on ratios, are
+        // unchanged, so the hardware reciprocal estimate serves as the scale
+        const T s = __builtin_amdgcn_rcpf(fmax(q0, fmax(q1, q2)));
         q0 *= s; q1 *= s; q2 *= s;
     }
     T n0, n1, n2;
