@@ -33,20 +33,20 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # + ww_update_dev.h (update).
 MEASURED_TRAFFIC = {
     # y sweep (the VALU roofline's kernel) and the fused x sweep
-    ("3fb913d5b1eeb477", "fp64", 512): {"read": 9.425e9, "write": 9.038e9,
+    ("a0e063ef9d6c6763", "fp64", 512): {"read": 9.425e9, "write": 9.038e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("3fb913d5b1eeb477", "fp32", 512): {"read": 4.799e9, "write": 4.703e9,
+    ("a0e063ef9d6c6763", "fp32", 512): {"read": 4.791e9, "write": 4.712e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
-    ("3fb913d5b1eeb477", "fp64_xfused", 512): {"read": 31.11e9, "write": 11.64e9,
+    ("a0e063ef9d6c6763", "fp64_xfused", 512): {"read": 31.32e9, "write": 11.64e9,
                                              "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("3fb913d5b1eeb477", "fp32_xfused", 512): {"read": 15.3e9, "write": 5.837e9,
+    ("a0e063ef9d6c6763", "fp32_xfused", 512): {"read": 15.25e9, "write": 5.837e9,
                                              "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 MEASURED_UPDATE_TRAFFIC = {
     # B-only update, mean over the profiled launches (RK stage forms and L(U))
-    ("cf6b38782c5af04b", "fp64", 512): {"read": 11.9e9, "write": 5.585e9,
+    ("cf6b38782c5af04b", "fp64", 512): {"read": 11.89e9, "write": 5.575e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("cf6b38782c5af04b", "fp32", 512): {"read": 5.743e9, "write": 2.818e9,
+    ("cf6b38782c5af04b", "fp32", 512): {"read": 5.743e9, "write": 2.817e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -55,10 +55,10 @@ MEASURED_UPDATE_TRAFFIC = {
 # valid only for the batched source they were taken on (sha256 of
 # ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
 MEASURED_BATCH_TRAFFIC = {
-    ("943fbd4c44bd95e6", 4096, 4): (85.52e9, 32.19e9),
-    ("943fbd4c44bd95e6", 4096, 8): (79.29e9, 32.73e9),
-    ("943fbd4c44bd95e6", 4096, 12): (80.90e9, 31.49e9),
-    ("943fbd4c44bd95e6", 4096, 16): (78.93e9, 32.49e9),
+    ("04358f0e738cee6d", 4096, 4): (85.48e9, 32.27e9),
+    ("04358f0e738cee6d", 4096, 8): (79.65e9, 32.73e9),
+    ("04358f0e738cee6d", 4096, 12): (80.99e9, 31.49e9),
+    ("04358f0e738cee6d", 4096, 16): (78.97e9, 32.47e9),
 }
 BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
 
