@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         cstr = 1;
         if (FUSED || F.cnt[0] >= sw::XSEG_MIN) {
             const sw::XSeg X = sw::xseg_setup(F, blockIdx.x);
-            sw::xseg_stage<float>(u, G, F, P, X, sq);
+            sw::xseg_stage<float, false, true>(u, G, F, P, X, sq);
             __syncthreads();
             sw::stage_end();
             act = sw::xseg_face(F, X, tid, pos, off);
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
                 if (row < nrows && x <= nlast) {
                     int j = F.lo[1] + row % F.cnt[1], k = F.lo[2] + row / F.cnt[1];
                     long id = G.base + x * G.s[0] + j * G.s[1] + k * G.s[2];
-                    sw::stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+                    sw::stage_cell<float, false, true>(u, id, G.sv, cm, P.gamma, sq + c, NC);
                 }
             }
             __syncthreads();
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(256) void routed_sweep_kernel(const float *__restri
         }
     } else {
         cstr = YZ_PW;
-        sw::yz_stage<DIR, YZ_PW, float>(u, G, F, P, blockIdx.x, blockIdx.y, sq);
+        sw::yz_stage<DIR, YZ_PW, float, true>(u, G, F, P, blockIdx.x, blockIdx.y, sq);
         __syncthreads();
         sw::stage_end();
         act = sw::yz_face<DIR, YZ_PW>(F, blockIdx.x, blockIdx.y, tid, pos, off);

@@ -236,8 +236,10 @@ __device__ __forceinline__ T cell_flux(const T (&w)[8], T p, T ir, T (&F)[7])
 }
 
 // Stage one cell from its sweep-frame conserved variables w (rho, mn, mt1,
-// mt2, Bn, Bt1, Bt2, E): the variables and the derived quantities.
-template <typename T, bool PRE = false>
+// mt2, Bn, Bt1, Bt2, E): the variables and the derived quantities.  LIN:
+// slots 0..10 only (the learned router's routed sweeps: linear fluxes and
+// features need no c_s, c_A).
+template <typename T, bool PRE = false, bool LIN = false>
 __device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q, int qs)
 {
     const T r = w[0], mn = w[1], m1 = w[2], m2 = w[3], bn = w[4], b1 = w[5], b2 = w[6], e = w[7];
@@ -253,14 +255,16 @@ __device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q
     T dd = a2 - bn2;
     T disc = dd * dd + bt2 * (T(2) * a2 + T(2) * bn2 + bt2);
     T cf2 = T(0.5) * (a2 + bn2 + bt2 + fsqrt(disc));
-    T cs2 = a2 * bn2 * frcp(cf2);
+    T cs2 = a2 * bn2 * frcp(cf2);       // (unused, and not computed, with LIN)
     q[0 * qs] = r;  q[1 * qs] = mn; q[2 * qs] = m1; q[3 * qs] = m2;
     q[4 * qs] = bn; q[5 * qs] = b1; q[6 * qs] = b2; q[7 * qs] = e;
     q[8 * qs] = p;
     q[9 * qs] = ir;
     q[10 * qs] = fsqrt(cf2);
-    q[11 * qs] = fsqrt(cs2);
-    q[12 * qs] = fsqrt(bn2);
+    if constexpr (!LIN) {
+        q[11 * qs] = fsqrt(cs2);
+        q[12 * qs] = fsqrt(bn2);
+    }
     if constexpr (PRE) {
         T F[7];
         const T vn = cell_flux(w, p, ir, F);
@@ -271,14 +275,14 @@ __device__ __forceinline__ void stage_values(const T (&w)[8], double gamma, T *q
 }
 
 // Stage one cell: its variables read from the state (cm: sweep-frame order).
-template <typename T, bool PRE = false>
+template <typename T, bool PRE = false, bool LIN = false>
 __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, long sv,
                                            const int (&cm)[8], double gamma, T *q, int qs)
 {
     T w[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) w[v] = u[id + cm[v] * sv];
-    stage_values<T, PRE>(w, gamma, q, qs);
+    stage_values<T, PRE, LIN>(w, gamma, q, qs);
 }
 
 // Stage cells c = tid, tid + 256, ... (< ncell, at most IT per thread) of a
@@ -287,7 +291,7 @@ __device__ __forceinline__ void stage_cell(const T *__restrict__ u, long id, lon
 // together rather than one cell's latency after another's, which matters at
 // two waves per SIMD.  cell_id(c, id) gives the state index of tile cell c,
 // false if the cell is not staged; c's LDS slot is sq + c.
-template <int IT, bool PRE = false, typename T, typename CellId>
+template <int IT, bool PRE = false, bool LIN = false, typename T, typename CellId>
 __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, const int (&cm)[8], double gamma,
                                            T *sq, int qs, int ncell, CellId cell_id)
 {
@@ -306,7 +310,7 @@ __device__ __forceinline__ void stage_tile(const T *__restrict__ u, long sv, con
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-        if (ok[it]) stage_values<T, PRE>(w[it], gamma, sq + tid + it * TILE * ROWS, qs);
+        if (ok[it]) stage_values<T, PRE, LIN>(w[it], gamma, sq + tid + it * TILE * ROWS, qs);
 }
 
 // Interface flux from six staged cells.  sq: LDS base, qs: stride between
@@ -539,7 +543,10 @@ __device__ __forceinline__ void face_flux(const T *__restrict__ sq, int qs, int 
 // flux of interfaces the learned router calls smooth): one Lax-Friedrichs
 // speed alpha = max(|v_n| + c_f) over the stencil for every component and
 // the linear-weight form of eq. (1), (2,-13,47,27,-3)/60 on F^+ and the
-// mirror (-3,27,47,-13,2)/60 on F^-.
+// mirror (-3,27,47,-13,2)/60 on F^-.  With F^+- = (F +- alpha U)/2 the two
+// stencils add up to the sixth-order central combination of F,
+// (1,-8,37,37,-8,1)/60, plus alpha times the fifth difference of U,
+// (1,-5,10,-10,5,-1)/60: the same flux in 12 operations per component.
 template <typename T>
 __device__ __forceinline__ void linear_flux(const T *__restrict__ sq, int qs, int off, int cstr,
                                             T (&out)[7])
@@ -560,18 +567,11 @@ __device__ __forceinline__ void linear_flux(const T *__restrict__ sq, int qs, in
         al = fmax(al, fabs(vn) + cf);
     }
 #undef QL
-    const T h = T(0.5) * al;
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-        T pp[6], mm[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            pp[j] = fma(h, U[j][c], T(0.5) * F[j][c]);
-            mm[j] = fma(-h, U[j][c], T(0.5) * F[j][c]);
-        }
-        out[c] = (T(2) * pp[0] - T(13) * pp[1] + T(47) * pp[2] + T(27) * pp[3] - T(3) * pp[4]
-                  - T(3) * mm[1] + T(27) * mm[2] + T(47) * mm[3] - T(13) * mm[4] + T(2) * mm[5])
-                 * T(1.0 / 60.0);
+        const T cen = fma(T(37), F[2][c] + F[3][c], fma(T(-8), F[1][c] + F[4][c], F[0][c] + F[5][c]));
+        const T dis = fma(T(10), U[2][c] - U[3][c], fma(T(-5), U[1][c] - U[4][c], U[0][c] - U[5][c]));
+        out[c] = fma(al, dis, cen) * T(1.0 / 60.0);
     }
 }
 
@@ -948,12 +948,13 @@ __device__ __forceinline__ XSeg xseg_setup(const FaceBox &F, long tile, int stri
 }
 
 // Stage the tile's cells (x sweep frame), sq with stride XSEG_CELLS.
-template <typename T, bool PRE = false>
+template <typename T, bool PRE = false, bool LIN = false>
 __device__ __forceinline__ void xseg_stage(const T *__restrict__ u, const Geom &G, const FaceBox & /*F*/,
                                            const Phys &P, const XSeg &X, T *sq)
 {
     const int cm[8] = { 0, 1, 2, 3, 4, 5, 6, 7 };
-    stage_tile<(XSEG_CELLS + 255) / 256, PRE>(u, G.sv, cm, P.gamma, sq, XSEG_CELLS, X.o4, [&](int c, long &id) {
+    stage_tile<(XSEG_CELLS + 255) / 256, PRE, LIN>(u, G.sv, cm, P.gamma, sq, XSEG_CELLS, X.o4,
+                                                  [&](int c, long &id) {
         const int s = (c >= X.o1) + (c >= X.o2) + (c >= X.o3);
         const int x = X.fa(s) - 3 + (c - X.off(s));
         id = G.base + x * G.s[0] + X.j(s) * G.s[1] + (long)X.k(s) * G.s[2];
@@ -1056,7 +1057,7 @@ __device__ __forceinline__ void sweep_tile_xseg_fused(const T *__restrict__ u, T
 template <int PW>
 __host__ __device__ constexpr int yz_cells() { return PW * (256 / PW + 5); }
 
-template <int DIR, int PW, typename T>
+template <int DIR, int PW, typename T, bool LIN = false>
 __device__ __forceinline__ void yz_stage(const T *__restrict__ u, const Geom &G, const FaceBox &F,
                                          const Phys &P, int ta, int tb, T *sq)
 {
@@ -1076,7 +1077,7 @@ __device__ __forceinline__ void yz_stage(const T *__restrict__ u, const Geom &G,
         if (p < npos && y <= nlast) {
             const int ca = F.lo[A] + p % F.cnt[A], cb = F.lo[B] + p / F.cnt[A];
             const long id = G.base + ca * G.s[A] + cb * G.s[B] + (long)y * G.s[N];
-            stage_cell(u, id, G.sv, cm, P.gamma, sq + c, NC);
+            stage_cell<T, false, LIN>(u, id, G.sv, cm, P.gamma, sq + c, NC);
         }
     }
 }
