@@ -27,6 +27,31 @@ def test_linear_flux_equals_characteristic_flux_with_linear_weights(orc):
         assert np.abs(Fc - Fl).max() < 1e-13 * (1 + np.abs(Fl).max())
 
 
+def test_linear_flux_central_plus_dissipation_form(orc):
+    # The GPU evaluates the linear flux as (1,-8,37,37,-8,1)/60 F plus
+    # alpha (1,-5,10,-10,5,-1)/60 U; with F+- = (F +- alpha U)/2 that is the
+    # oracle's upwind pair (2,-13,47,27,-3)/60 on F+ and its mirror on F-.
+    # Checked here against the oracle's own linear flux on smooth and on
+    # discontinuous stencils, alpha = max(|v_n| + c_f) over the stencil.
+    cen = np.array([1.0, -8.0, 37.0, 37.0, -8.0, 1.0]) / 60.0
+    dis = np.array([1.0, -5.0, 10.0, -10.0, 5.0, -1.0]) / 60.0
+    keep = [0, 1, 2, 3, 5, 6, 7]                      # every component but B_n
+    rng = np.random.default_rng(11)
+    for seed in range(12):
+        if seed < 8:
+            Us = smooth_stencil(orc, 0.2, seed)
+        else:
+            WL = np.concatenate([[rng.uniform(0.2, 2)], rng.normal(size=6), [rng.uniform(0.1, 2)]])
+            WR = np.concatenate([[rng.uniform(0.2, 2)], rng.normal(size=6), [rng.uniform(0.1, 2)]])
+            WR[4] = WL[4]
+            Us = np.array([orc.prim_to_cons(WL if j < 3 else WR) for j in range(6)])
+        F = np.array([orc.flux(U, 0) for U in Us])
+        alpha = max(abs(U[1] / U[0]) + orc.wave_speeds(U, 0)[0] for U in Us)
+        mine = cen @ F + alpha * (dis @ Us)
+        ref = orc.linear_flux(Us)
+        assert np.abs(mine[keep] - ref[keep]).max() < 1e-13 * (1 + np.abs(ref).max() + alpha * np.abs(Us).max())
+
+
 def test_linear_flux_consistency_and_upwinding(orc):
     # uniform stencil -> physical flux; supersonic flow to the right -> the
     # F^- part vanishes only if alpha = |v| + c_f, which it is.
