@@ -988,12 +988,8 @@ __device__ __forceinline__ void sweep_tile_xseg(const T *__restrict__ u, T *__re
     int pos[3], off;
     if (xseg_face(F, X, threadIdx.x + TILE * threadIdx.y, pos, off)) {
         T out[7];
-        // FP64 x segments: the folded phi_n needs the two scaled epsilons
-        // live across the fields, which pushes this kernel past 256 VGPRs
-        // (a scratch spill of ~2.7 GB of writes per 512^3 launch); the
-        // plain form fits and runs as fast
-        face_flux<T, false, WZ, GLF, (sizeof(T) == 4), PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps,
-                                                              out, nullptr, P.ag);
+        face_flux<T, false, WZ, GLF, true, PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out, nullptr,
+                                                P.ag);
         store_face<0, T>(flux, F, pos, out);
     }
 }
@@ -1026,8 +1022,8 @@ __device__ __forceinline__ void sweep_tile_xseg_fused(const T *__restrict__ u, T
     const bool valid = xseg_face(F, X, tid, pos, off);
     if (valid) {
         T out[7];
-        face_flux<T, false, WZ, GLF, (sizeof(T) == 4), PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps,
-                                                              out, nullptr, P.ag);
+        face_flux<T, false, WZ, GLF, true, PRE>(sq, XSEG_CELLS, off, 1, P.gamma, P.igm1, (T)P.eps, out, nullptr,
+                                                P.ag);
         hx[0 * NH + tid] = out[0];
         hx[1 * NH + tid] = out[1];
         hx[2 * NH + tid] = out[2];
