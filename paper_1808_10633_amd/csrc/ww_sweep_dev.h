@@ -80,11 +80,13 @@ __device__ __forceinline__ float frcp_w(float x) { return __builtin_amdgcn_rcpf(
 
 // Square root in FP64 for finite x >= 0: the hardware reciprocal-square-root
 // estimate, one Goldschmidt step towards g = sqrt(x), h = 1/(2 sqrt(x)), then
-// two Newton corrections g += (x - g^2) h with the residual formed by a fused
-// multiply-add (Markstein's formulation).  The estimate is taken at
-// x + 2^-1022, so x = 0 gives 0 and x < 0 gives NaN; the wave speeds and
-// normalisations passed here are never subnormal or infinite, so the range
-// scaling and special-case selects of the general routine are left out.
+// a Newton correction g += (x - g^2) h with the residual formed by a fused
+// multiply-add (Markstein's formulation).  With exactly rounded FMAs the
+// result is the correctly rounded root for estimate errors up to 2^-22 and
+// within 1 ulp up to 2^-14.  The estimate is taken at x + 2^-1022, so x = 0
+// gives 0 and x < 0 gives NaN; the wave speeds and normalisations passed here
+// are never subnormal or infinite, so the range scaling and special-case
+// selects of the general routine are left out.
 __device__ __forceinline__ double fsqrt(double x)
 {
     const double y = __builtin_amdgcn_rsq(x + 0x1p-1022);
@@ -92,9 +94,7 @@ __device__ __forceinline__ double fsqrt(double x)
     const double r = fma(-g, h, 0.5);
     g = fma(g, r, g);
     h = fma(h, r, h);
-    double d = fma(-g, g, x);
-    g = fma(d, h, g);
-    d = fma(-g, g, x);
+    const double d = fma(-g, g, x);
     return fma(d, h, g);
 }
 __device__ __forceinline__ float fsqrt(float x) { return sqrtf(x); }

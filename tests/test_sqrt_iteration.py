@@ -1,11 +1,12 @@
 """The FP64 square-root and reciprocal-square-root iterations of the sweep
-kernels (hardware estimate, one Goldschmidt step, two Newton corrections of
+kernels (hardware estimate, one Goldschmidt step, one Newton correction of
 the root with an FMA residual; two Newton steps for the reciprocal root),
 emulated on the CPU with exactly rounded fused multiply-adds.  The estimate
-is modelled as 1/sqrt(x) with a relative error up to E, far above the error
-of the hardware estimate; the pins are facts of the iteration: the root is
-the correctly rounded one, the reciprocal root within 2 ulp, sqrt(0) = 0 and
-a negative argument gives NaN."""
+is modelled as 1/sqrt(x) with a relative error up to E (the hardware
+estimate's measured error is below 2^-22); the pins are facts of the
+iteration: the root is the correctly rounded one for E up to 2^-22 and
+within 1 ulp for E up to 2^-14, the reciprocal root within 2 ulp,
+sqrt(0) = 0 and a negative argument gives NaN."""
 import math
 import random
 from fractions import Fraction
@@ -31,8 +32,6 @@ def _fsqrt(x, err):
     r = _fma(-g, h, 0.5)
     g, h = _fma(g, r, g), _fma(h, r, h)
     d = _fma(-g, g, x)
-    g = _fma(d, h, g)
-    d = _fma(-g, g, x)
     return _fma(d, h, g)
 
 
@@ -43,13 +42,13 @@ def _frsq(x, err):
     return y
 
 
-@pytest.mark.parametrize("emax", [2.0 ** -22, 2.0 ** -14])
-def test_root_correctly_rounded_and_reciprocal_within_two_ulp(emax):
+@pytest.mark.parametrize("emax,root_ulp", [(2.0 ** -22, 0), (2.0 ** -14, 1)])
+def test_root_rounding_and_reciprocal_within_two_ulp(emax, root_ulp):
     rnd = random.Random(7)
     for _ in range(3000):
         x = 10.0 ** rnd.uniform(-250, 250) * rnd.uniform(1.0, 10.0)
         err = rnd.uniform(-emax, emax)
-        assert _fsqrt(x, err) == math.sqrt(x)
+        assert abs(_fsqrt(x, err) - math.sqrt(x)) <= root_ulp * math.ulp(math.sqrt(x))
         want = 1.0 / math.sqrt(x)
         assert abs(_frsq(x, err) - want) <= 2 * math.ulp(want)
 
