@@ -33,20 +33,20 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (packed)
 # + ww_update_dev.h (update).
 MEASURED_TRAFFIC = {
     # y sweep (the VALU roofline's kernel) and the fused x sweep
-    ("63724ec5d3dfc29f", "fp64", 512): {"read": 9.426e9, "write": 9.038e9,
+    ("b97c660155bc5f2d", "fp64", 512): {"read": 9.406e9, "write": 9.05e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("63724ec5d3dfc29f", "fp32", 512): {"read": 4.79e9, "write": 4.712e9,
+    ("b97c660155bc5f2d", "fp32", 512): {"read": 4.788e9, "write": 4.711e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
-    ("63724ec5d3dfc29f", "fp64_xfused", 512): {"read": 31.1e9, "write": 11.64e9,
+    ("b97c660155bc5f2d", "fp64_xfused", 512): {"read": 31.23e9, "write": 11.64e9,
                                              "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("63724ec5d3dfc29f", "fp32_xfused", 512): {"read": 15.26e9, "write": 5.837e9,
+    ("b97c660155bc5f2d", "fp32_xfused", 512): {"read": 15.24e9, "write": 5.837e9,
                                              "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 MEASURED_UPDATE_TRAFFIC = {
     # B-only update, mean over the profiled launches (RK stage forms and L(U))
-    ("cf6b38782c5af04b", "fp64", 512): {"read": 11.9e9, "write": 5.585e9,
+    ("cf6b38782c5af04b", "fp64", 512): {"read": 11.8e9, "write": 5.585e9,
                                       "profile": "profiles/fp64_512_turbulence_trace_and_hbm.md"},
-    ("cf6b38782c5af04b", "fp32", 512): {"read": 5.744e9, "write": 2.818e9,
+    ("cf6b38782c5af04b", "fp32", 512): {"read": 5.73e9, "write": 2.818e9,
                                       "profile": "profiles/fp32_512_turbulence_trace_and_hbm.md"},
 }
 
@@ -55,10 +55,10 @@ MEASURED_UPDATE_TRAFFIC = {
 # valid only for the batched source they were taken on (sha256 of
 # ww_batch.hip, ww_batch.h, ww_sweep_dev.h, ww_update_dev.h, ww_internal.h).
 MEASURED_BATCH_TRAFFIC = {
-    ("a49af6fb6c8485e1", 4096, 4): (85.49e9, 32.27e9),
-    ("a49af6fb6c8485e1", 4096, 8): (79.64e9, 32.73e9),
-    ("a49af6fb6c8485e1", 4096, 12): (80.99e9, 31.49e9),
-    ("a49af6fb6c8485e1", 4096, 16): (78.97e9, 32.48e9),
+    ("357f8b2041d60ec0", 4096, 4): (85.48e9, 32.26e9),
+    ("357f8b2041d60ec0", 4096, 8): (79.57e9, 32.72e9),
+    ("357f8b2041d60ec0", 4096, 12): (81.07e9, 31.47e9),
+    ("357f8b2041d60ec0", 4096, 16): (79.07e9, 32.45e9),
 }
 BATCH_TRAFFIC_PROFILE = "profiles/batched_4096_patches_hbm.md"
 
